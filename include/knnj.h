@@ -1,0 +1,180 @@
+/*
+ * knnj -- exact K-nearest-neighbour join of high-dimensional sparse vectors on
+ * one AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The operation (Problem definition, Sec. 3): for every vector r of R, return
+ * the k vectors s of S with the largest score dot(r, s) = sum_d r[d] * s[d]
+ * (Eq. 1), where a sparse vector is a list of features (d, w), ascending d,
+ * w > 0.  Reading used throughout: a neighbour must have score > 0 (the
+ * selection rule starts from a pruning score of 0, Algorithm 1 line 3 and
+ * Algorithm 2 line 5); neighbours are ordered by (score descending, S row id
+ * ascending), which also decides ties at the k-th place; a query with fewer
+ * than k positive-score vectors gets padding slots (id -1, score 0).
+ *
+ * Algorithms (Sec. 4): BF (Algorithm 2), IIB (inverted-index accumulation,
+ * Algorithm 3) and IIIB (threshold-refined inverted index, Algorithm 4), run
+ * as a block nested loop (Algorithm 1) over tiles of S.  All three return the
+ * same result (Theorem 1).
+ *
+ * Memory: every array argument named "device" is HIP device memory that the
+ * caller owns; the library never frees it.  The library owns the opaque
+ * index and MLP objects (released with their _free calls).  Calls are
+ * asynchronous on the given stream (a hipStream_t passed as void*, NULL for
+ * the default stream) unless stated otherwise; output buffers are valid after
+ * the stream is synchronised.
+ *
+ * Errors: every call returns a knnj_status; on failure nothing is written to
+ * the outputs (unless stated) and knnj_last_error() returns a message for the
+ * calling thread.
+ */
+#ifndef KNNJ_H
+#define KNNJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KNNJ_OK = 0,
+  KNNJ_EINVAL = -1,      /* bad argument or malformed CSR input */
+  KNNJ_ENOMEM = -2,      /* device allocation failed */
+  KNNJ_EDEVICE = -3,     /* a HIP runtime call failed */
+  KNNJ_EOVERFLOW = -4,   /* an integer score could exceed 2^31 - 1 */
+  KNNJ_EUNSUPPORTED = -5 /* valid input outside what this build handles */
+} knnj_status;
+
+/* Value type of a sparse matrix. */
+typedef enum {
+  KNNJ_U8 = 0,  /* uint8 weights in [1, 255]; scores are exact int32 */
+  KNNJ_F32 = 1  /* finite float32 weights > 0; scores are float32 */
+} knnj_dtype;
+
+/* In-memory join algorithm run on each (query group, S tile) pair. */
+typedef enum {
+  KNNJ_IIB = 0, /* Algorithm 3: walk the whole posting list of every query feature */
+  KNNJ_IIIB = 1 /* Algorithm 4: walk only the indexed part, then complete candidates */
+} knnj_algo;
+
+/*
+ * Sparse matrix in CSR form, all arrays in device memory.
+ *   indptr  int64[n_rows + 1], indptr[0] = 0, non-decreasing, indptr[n_rows] = nnz
+ *   indices int32[nnz], strictly ascending within each row, each in [0, n_dims)
+ *   values  uint8[nnz] (KNNJ_U8, every value >= 1) or float32[nnz] (KNNJ_F32,
+ *           finite and > 0)
+ * Rows may be empty.  A row may hold at most 4096 features.
+ */
+typedef struct {
+  int64_t n_rows;
+  int32_t n_dims;
+  int32_t dtype; /* knnj_dtype */
+  int64_t nnz;
+  const int64_t* indptr;
+  const int32_t* indices;
+  const void* values;
+} knnj_csr;
+
+typedef struct knnj_index knnj_index;
+
+/* Options of knnj_build_index (pass NULL for defaults). */
+typedef struct {
+  /* S tile width T: rows of S whose scores are accumulated together in one
+   * workgroup's local memory (the block B_s of Algorithm 1).  0 selects the
+   * default; otherwise a power of two in [256, 65536]. */
+  int32_t tile_width;
+  int32_t reserved[7];
+} knnj_index_opts;
+
+/* Flags of knnj_join_opts.flags */
+#define KNNJ_FLAG_NO_VALIDATE 1u /* skip the device check of R's CSR structure (no host sync) */
+
+/* Counters accumulated into knnj_join_opts.stats (device uint64[KNNJ_STAT_COUNT]). */
+enum {
+  KNNJ_STAT_POSTINGS = 0,   /* posting entries walked (IIB: the 2nd term of Eq. 4) */
+  KNNJ_STAT_COMPLETION = 1, /* IIIB: unindexed features read to complete candidates */
+  KNNJ_STAT_CANDIDATES = 2, /* IIIB: (query, s) pairs completed */
+  KNNJ_STAT_FALLBACKS = 3,  /* queries recomputed without the seeded threshold */
+  KNNJ_STAT_COUNT = 8
+};
+
+/* Options of knnj_join (pass NULL for defaults: IIB, validation on). */
+typedef struct {
+  int32_t algo;          /* knnj_algo */
+  uint32_t flags;        /* KNNJ_FLAG_* */
+  /* IIIB: rows of R per block whose statistics (dimension order and per-dimension
+   * maximum weight, Algorithm 4 lines 6-7) define the refinement bound; 0 means
+   * all of R is one block. */
+  int64_t r_block_rows;
+  /* Optional device float[n_rows of R]: a per-query guess of the k-th score used
+   * to seed IIIB's threshold before any posting is read.  Results stay exact: a
+   * query whose seed turns out too high is recomputed without it. */
+  const float* theta_seed;
+  /* Optional device uint64[KNNJ_STAT_COUNT]; counters are added to it. */
+  uint64_t* stats;
+  /* Optional device uint8[n_rows of R]: set to 1 for queries that fell back. */
+  uint8_t* fallback_out;
+  int32_t reserved[6];
+} knnj_join_opts;
+
+/*
+ * Build the inverted index of S (Algorithm 3, Create_Inverted_List_IIB): the
+ * posting list I_d of every dimension, split by S tile so that one tile's
+ * score accumulators fit in a workgroup's local memory; inside each
+ * (tile, d) list the entries are in ascending S row id.  The index keeps its
+ * own copy of everything it needs; S may be freed after the stream is
+ * synchronised.  Validates S on the device and synchronises the stream.
+ * Errors: EINVAL (malformed S, bad options), ENOMEM, EDEVICE, EUNSUPPORTED.
+ */
+knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void* stream, knnj_index** out);
+
+/* Host-side facts about a built index (sizes; no device data copied). */
+typedef struct {
+  int64_t n_rows;
+  int32_t n_dims;
+  int32_t dtype;
+  int64_t nnz;
+  int32_t tile_width;
+  int32_t n_tiles;
+  int32_t max_row_nnz;
+  int32_t reserved;
+} knnj_index_info;
+
+knnj_status knnj_index_info_get(const knnj_index* ix, knnj_index_info* out);
+
+/* Copy |I_d|, the length of every posting list over all of S (Sec. 4.3), into
+ * out (device uint32[n_dims], caller-owned).  Asynchronous on stream. */
+knnj_status knnj_index_list_lengths(const knnj_index* ix, uint32_t* out, void* stream);
+
+void knnj_index_free(knnj_index* ix);
+
+/*
+ * Exact KNN join of R against the indexed S (Algorithm 1 with Algorithm 3 or 4
+ * as the in-memory join).  k in [1, 1024].  Outputs (device, row-major, k per
+ * query): out_ids int32[n_rows*k], out_scores int32 (U8) or float (F32)
+ * [n_rows*k], out_count int32[n_rows] (may be NULL).  Row i holds
+ * min(k, #{s : score > 0}) neighbours in (score desc, id asc) order, then
+ * padding (-1, 0).
+ * Validation: host checks of shapes and options; unless KNNJ_FLAG_NO_VALIDATE,
+ * a device check of R's structure followed by a stream synchronisation.
+ * Errors: EINVAL, EOVERFLOW (u8 scores could exceed 2^31-1), ENOMEM, EDEVICE.
+ */
+knnj_status knnj_join(const knnj_index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt,
+                      int32_t* out_ids, void* out_scores, int32_t* out_count, void* stream);
+
+/*
+ * Brute-force join (Algorithm 2): every pair's score by a merge of the two
+ * sorted feature lists.  Same outputs, validation and errors as knnj_join.
+ */
+knnj_status knnj_join_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* out_ids, void* out_scores,
+                         int32_t* out_count, void* stream);
+
+/* Thread-local description of the last failure ("" if none). */
+const char* knnj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNNJ_H */

@@ -1,0 +1,265 @@
+// C-ABI entry points: argument checks, object lifetime, kernel sequencing.
+#include <string.h>
+
+#include <string>
+
+#include "common.hpp"
+
+namespace knnj {
+
+static thread_local std::string g_last_error;
+
+knnj_status fail(knnj_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+knnj_status validate_csr(const knnj_csr* m, int32_t* dev_err, hipStream_t st, int32_t* max_row);
+knnj_status build_postings(Index* ix, const int64_t* indptr, const int32_t* indices, const void* values,
+                           hipStream_t st);
+knnj_status launch_init_out(int64_t n_rows, int32_t k, int32_t* ids, void* sc, int32_t* cnt, hipStream_t st);
+knnj_status launch_reduce_stats(const uint64_t* slots, uint64_t* out, hipStream_t st);
+knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
+                       uint64_t* slots, hipStream_t st);
+knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids, void* sc,
+                        int32_t* cnt, uint64_t* slots, hipStream_t st);
+knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
+                      hipStream_t st);
+knnj_status set_smem_limits(int max_smem);
+size_t tile_smem_bytes(int tile);
+
+static knnj_status check_csr_host(const knnj_csr* m, const char* name) {
+  if (!m) return fail(KNNJ_EINVAL, std::string(name) + " is NULL");
+  if (m->dtype != KNNJ_U8 && m->dtype != KNNJ_F32) return fail(KNNJ_EINVAL, std::string(name) + ": unknown dtype");
+  if (m->n_rows < 0 || m->nnz < 0 || m->n_dims < 1)
+    return fail(KNNJ_EINVAL, std::string(name) + ": negative size or n_dims < 1");
+  if (m->n_rows > 0x7fffffffll) return fail(KNNJ_EUNSUPPORTED, std::string(name) + ": more than 2^31-1 rows");
+  if (!m->indptr) return fail(KNNJ_EINVAL, std::string(name) + ": indptr is NULL");
+  if (m->nnz > 0 && (!m->indices || !m->values))
+    return fail(KNNJ_EINVAL, std::string(name) + ": indices/values are NULL");
+  return KNNJ_OK;
+}
+
+static int device_max_smem(int dev) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+  return v;
+}
+
+static void free_index(Index* ix) {
+  if (!ix) return;
+  (void)hipFree(ix->offsets);
+  (void)hipFree(ix->post_u8);
+  (void)hipFree(ix->post_s);
+  (void)hipFree(ix->post_w);
+  (void)hipFree(ix->list_len);
+  (void)hipFree(ix->s_indptr);
+  (void)hipFree(ix->s_indices);
+  (void)hipFree(ix->s_values);
+  (void)hipFree(ix->iiib_post);
+  (void)hipFree(ix->iiib_post_w);
+  (void)hipFree(ix->iiib_post_s);
+  (void)hipFree(ix->iiib_fwd);
+  (void)hipFree(ix->iiib_fwd_w);
+  (void)hipFree(ix->iiib_cut);
+  (void)hipFree(ix->rec_tmp);
+  (void)hipFree(ix->dev_err);
+  (void)hipFree(ix->stat_slots);
+  delete ix;
+}
+
+}  // namespace knnj
+
+using namespace knnj;
+
+// The public handle is the internal Index itself, seen through an opaque type.
+static Index* impl(const knnj_index* h) { return reinterpret_cast<Index*>(const_cast<knnj_index*>(h)); }
+
+extern "C" {
+
+const char* knnj_last_error(void) { return g_last_error.c_str(); }
+
+knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void* stream, knnj_index** out) {
+  g_last_error.clear();
+  if (!out) return fail(KNNJ_EINVAL, "out is NULL");
+  *out = nullptr;
+  knnj_status rc = check_csr_host(S, "S");
+  if (rc != KNNJ_OK) return rc;
+  int tile = opt && opt->tile_width ? opt->tile_width : 8192;
+  if (tile < 256 || tile > 65536 || (tile & (tile - 1)))
+    return fail(KNNJ_EINVAL, "tile_width must be a power of two in [256, 65536]");
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  KNNJ_HIP(hipGetDevice(&dev));
+  const int max_smem = device_max_smem(dev);
+  if (tile_smem_bytes(tile) > size_t(max_smem))
+    return fail(KNNJ_EUNSUPPORTED, "tile_width too large for this device's local memory (" +
+                                       std::to_string(max_smem) + " bytes per workgroup)");
+  if ((rc = set_smem_limits(max_smem)) != KNNJ_OK) return rc;
+  Index* ix = new Index();
+  ix->device = dev;
+  ix->n_rows = S->n_rows;
+  ix->n_dims = S->n_dims;
+  ix->dtype = S->dtype;
+  ix->nnz = S->nnz;
+  ix->tile = tile;
+  ix->log2_tile = 0;
+  while ((1 << ix->log2_tile) < tile) ++ix->log2_tile;
+  ix->n_tiles = int32_t((S->n_rows + tile - 1) / tile);
+  if (ix->n_tiles < 1) ix->n_tiles = 1;
+  const size_t vbytes = S->dtype == KNNJ_U8 ? 1 : 4;
+  const size_t nnz1 = size_t(S->nnz > 0 ? S->nnz : 1);
+  if (hipMalloc(&ix->dev_err, 4 * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&ix->stat_slots, sizeof(uint64_t) * 256 * KNNJ_STAT_COUNT) != hipSuccess) {
+    free_index(ix);
+    return fail(KNNJ_ENOMEM, "device allocation failed");
+  }
+  int32_t max_row = 0;
+  if ((rc = validate_csr(S, ix->dev_err, st, &max_row)) != KNNJ_OK) {
+    free_index(ix);
+    return rc;
+  }
+  ix->max_row_nnz = max_row;
+  if (hipMalloc(&ix->s_indptr, sizeof(int64_t) * (S->n_rows + 1)) != hipSuccess ||
+      hipMalloc(&ix->s_indices, sizeof(int32_t) * nnz1) != hipSuccess ||
+      hipMalloc(&ix->s_values, vbytes * nnz1) != hipSuccess ||
+      (S->dtype == KNNJ_U8 ? hipMalloc(&ix->post_u8, sizeof(uint32_t) * nnz1)
+                           : (hipMalloc(&ix->post_s, sizeof(uint16_t) * nnz1) == hipSuccess
+                                  ? hipMalloc(&ix->post_w, sizeof(float) * nnz1)
+                                  : hipErrorOutOfMemory)) != hipSuccess) {
+    free_index(ix);
+    return fail(KNNJ_ENOMEM, "device allocation for the index failed");
+  }
+  if (hipMemcpyAsync(ix->s_indptr, S->indptr, sizeof(int64_t) * (S->n_rows + 1), hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
+      (S->nnz > 0 &&
+       (hipMemcpyAsync(ix->s_indices, S->indices, sizeof(int32_t) * S->nnz, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(ix->s_values, S->values, vbytes * S->nnz, hipMemcpyDeviceToDevice, st) != hipSuccess))) {
+    free_index(ix);
+    return fail(KNNJ_EDEVICE, "copy of S into the index failed");
+  }
+  if ((rc = build_postings(ix, ix->s_indptr, ix->s_indices, ix->s_values, st)) != KNNJ_OK) {
+    free_index(ix);
+    return rc;
+  }
+  *out = reinterpret_cast<knnj_index*>(ix);
+  return KNNJ_OK;
+}
+
+knnj_status knnj_index_info_get(const knnj_index* h, knnj_index_info* out) {
+  if (!h || !out) return fail(KNNJ_EINVAL, "NULL argument");
+  const Index* ix = impl(h);
+  memset(out, 0, sizeof(*out));
+  out->n_rows = ix->n_rows;
+  out->n_dims = ix->n_dims;
+  out->dtype = ix->dtype;
+  out->nnz = ix->nnz;
+  out->tile_width = ix->tile;
+  out->n_tiles = ix->n_tiles;
+  out->max_row_nnz = ix->max_row_nnz;
+  return KNNJ_OK;
+}
+
+knnj_status knnj_index_list_lengths(const knnj_index* h, uint32_t* out, void* stream) {
+  if (!h || !out) return fail(KNNJ_EINVAL, "NULL argument");
+  const Index* ix = impl(h);
+  KNNJ_HIP(hipMemcpyAsync(out, ix->list_len, sizeof(uint32_t) * ix->n_dims, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+  return KNNJ_OK;
+}
+
+void knnj_index_free(knnj_index* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  free_index(impl(h));
+}
+
+static knnj_status check_join_args(const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t n_dims,
+                                   int32_t dtype) {
+  knnj_status rc = check_csr_host(R, "R");
+  if (rc != KNNJ_OK) return rc;
+  if (R->n_dims != n_dims) return fail(KNNJ_EINVAL, "R.n_dims differs from S.n_dims");
+  if (R->dtype != dtype) return fail(KNNJ_EINVAL, "R.dtype differs from S.dtype");
+  if (k < 1 || k > kMaxK) return fail(KNNJ_EINVAL, "k must be in [1, 1024]");
+  if (R->n_rows > 0 && (!ids || !sc)) return fail(KNNJ_EINVAL, "output buffers are NULL");
+  return KNNJ_OK;
+}
+
+static knnj_status overflow_check(int32_t dtype, int64_t max_r, int64_t max_s) {
+  if (dtype != KNNJ_U8) return KNNJ_OK;
+  const int64_t m = max_r < max_s ? max_r : max_s;
+  if (m * 65025ll > 0x7fffffffll) return fail(KNNJ_EOVERFLOW, "u8 scores could exceed 2^31-1");
+  return KNNJ_OK;
+}
+
+// Count buffer for callers that pass out_count = NULL (grow-only, per thread).
+static int32_t* scratch_count(int64_t n) {
+  static thread_local int32_t* buf = nullptr;
+  static thread_local int64_t cap = 0;
+  if (n > cap) {
+    if (buf) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(buf);
+    }
+    buf = nullptr;
+    cap = 0;
+    if (hipMalloc(&buf, sizeof(int32_t) * n) != hipSuccess) return nullptr;
+    cap = n;
+  }
+  return buf;
+}
+
+knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids,
+                      void* sc, int32_t* cnt, void* stream) {
+  g_last_error.clear();
+  if (!h) return fail(KNNJ_EINVAL, "index is NULL");
+  Index* ix = impl(h);
+  knnj_status rc = check_join_args(R, k, ids, sc, ix->n_dims, ix->dtype);
+  if (rc != KNNJ_OK) return rc;
+  knnj_join_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  if (o.algo != KNNJ_IIB && o.algo != KNNJ_IIIB) return fail(KNNJ_EINVAL, "unknown algo");
+  if (o.r_block_rows < 0) return fail(KNNJ_EINVAL, "r_block_rows must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  int32_t max_r = kMaxRowNnz;
+  if (!(o.flags & KNNJ_FLAG_NO_VALIDATE)) {
+    if ((rc = validate_csr(R, ix->dev_err, st, &max_r)) != KNNJ_OK) return rc;
+  }
+  if ((rc = overflow_check(ix->dtype, max_r, ix->max_row_nnz)) != KNNJ_OK) return rc;
+  if (R->n_rows == 0) return KNNJ_OK;
+  if (!cnt && !(cnt = scratch_count(R->n_rows))) return fail(KNNJ_ENOMEM, "count buffer allocation failed");
+  if ((rc = launch_init_out(R->n_rows, k, ids, sc, cnt, st)) != KNNJ_OK) return rc;
+  uint64_t* slots = nullptr;
+  if (o.stats) {
+    slots = ix->stat_slots;
+    KNNJ_HIP(hipMemsetAsync(slots, 0, sizeof(uint64_t) * 256 * KNNJ_STAT_COUNT, st));
+  }
+  if (o.algo == KNNJ_IIB) rc = launch_iib(ix, R, k, ids, sc, cnt, slots, st);
+  else rc = launch_iiib(ix, R, k, &o, ids, sc, cnt, slots, st);
+  if (rc != KNNJ_OK) return rc;
+  if (o.stats) return launch_reduce_stats(slots, o.stats, st);
+  return KNNJ_OK;
+}
+
+knnj_status knnj_join_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
+                         void* stream) {
+  g_last_error.clear();
+  knnj_status rc = check_csr_host(S, "S");
+  if (rc != KNNJ_OK) return rc;
+  if ((rc = check_join_args(R, k, ids, sc, S->n_dims, S->dtype)) != KNNJ_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  static thread_local int32_t* err = nullptr;
+  if (!err && hipMalloc(&err, 4 * sizeof(int32_t)) != hipSuccess) return fail(KNNJ_ENOMEM, "allocation failed");
+  int32_t max_s = 0, max_r = 0;
+  if ((rc = validate_csr(S, err, st, &max_s)) != KNNJ_OK) return rc;
+  if ((rc = validate_csr(R, err, st, &max_r)) != KNNJ_OK) return rc;
+  if ((rc = overflow_check(S->dtype, max_r, max_s)) != KNNJ_OK) return rc;
+  if (R->n_rows == 0) return KNNJ_OK;
+  if (!cnt && !(cnt = scratch_count(R->n_rows))) return fail(KNNJ_ENOMEM, "count buffer allocation failed");
+  if ((rc = launch_init_out(R->n_rows, k, ids, sc, cnt, st)) != KNNJ_OK) return rc;
+  return launch_bf(S, R, k, ids, sc, cnt, st);
+}
+
+}  // extern "C"

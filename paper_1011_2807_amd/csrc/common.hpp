@@ -1,0 +1,120 @@
+// Shared device helpers and the library's internal types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/knnj.h"
+
+namespace knnj {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;           // threads per workgroup for most kernels
+constexpr int kMaxK = 1024;           // largest k accepted by the join
+constexpr int kSortBuf = 2048;        // selection buffer entries (>= 2 * kMaxK)
+constexpr int kSegChunk = 512;        // query features staged per pass of the postings walk
+constexpr int kMaxRowNnz = 4096;      // longest row accepted
+constexpr int kLevels = 64;           // IIIB threshold levels
+
+// Status helper: record a message for knnj_last_error and return the code.
+knnj_status fail(knnj_status code, const std::string& msg);
+
+#define KNNJ_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::knnj::fail(KNNJ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// The opaque index (Algorithm 3's inverted lists split by S tile).
+struct Index {
+  int64_t n_rows = 0;
+  int32_t n_dims = 0;
+  int32_t dtype = KNNJ_U8;
+  int64_t nnz = 0;
+  int32_t tile = 0;      // T
+  int32_t log2_tile = 0;
+  int32_t n_tiles = 0;
+  int32_t max_row_nnz = 0;
+  int device = 0;
+  // offsets[t * n_dims + d] .. offsets[t * n_dims + d + 1] is list (t, d)
+  int64_t* offsets = nullptr;
+  // u8: one uint32 per entry, (s_local << 16) | (w << 8); f32: s_local uint16 + weight float
+  uint32_t* post_u8 = nullptr;
+  uint16_t* post_s = nullptr;
+  float* post_w = nullptr;
+  uint32_t* list_len = nullptr;  // |I_d| over all of S
+  // private copy of S (forward lists), used by the IIIB refinement
+  int64_t* s_indptr = nullptr;
+  int32_t* s_indices = nullptr;
+  void* s_values = nullptr;
+  // IIIB per-R-block index (rebuilt per block, grow-only buffers)
+  size_t iiib_cap_entries = 0;
+  uint32_t* iiib_post = nullptr;     // entries (s_local << 16) | (w << 8) | level
+  float* iiib_post_w = nullptr;      // f32 weights, same order
+  uint16_t* iiib_post_s = nullptr;   // f32 s_local, same order
+  uint32_t* iiib_fwd = nullptr;      // per S row, features in the block's order: (d << 14 ... ) see iiib.hip
+  float* iiib_fwd_w = nullptr;
+  uint16_t* iiib_cut = nullptr;      // per (tile, d, level): entries with level >= that level
+  size_t iiib_cut_cap = 0;
+  uint64_t* rec_tmp = nullptr;       // build scratch (8 bytes per entry)
+  size_t rec_cap = 0;
+  // small persistent scratch
+  int32_t* dev_err = nullptr;        // validation result
+  uint64_t* stat_slots = nullptr;    // spread counters, reduced into caller stats
+};
+
+// Element-type traits for the value arrays.
+template <typename V>
+struct ScoreOf;
+template <>
+struct ScoreOf<uint8_t> {
+  using T = uint32_t;
+};
+template <>
+struct ScoreOf<float> {
+  using T = float;
+};
+
+__device__ __forceinline__ uint32_t score_bits(uint32_t v) { return v; }
+__device__ __forceinline__ uint32_t score_bits(float v) { return __float_as_uint(v); }
+
+// Block-wide exclusive scan of one uint32 per thread (kBlock threads).
+// `tmp` needs kBlock / kWave + 1 words of shared memory.  Returns the exclusive
+// prefix; *total gets the block sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) tmp[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      uint32_t t = tmp[w];
+      tmp[w] = s;
+      s += t;
+    }
+    tmp[kBlock / kWave] = s;
+  }
+  __syncthreads();
+  uint32_t r = tmp[wid] + x - v;
+  *total = tmp[kBlock / kWave];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* tmp) {
+  uint32_t total;
+  (void)block_exclusive_scan(v, tmp, &total);
+  return total;
+}
+
+}  // namespace knnj

@@ -1,0 +1,229 @@
+"""Python binding of libknnj.so (ctypes).  Argument marshalling only.
+
+Every step of the join runs in the library's HIP kernels; PyTorch supplies
+device memory and the current stream.  The binding fails loudly when the
+library is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libknnj.so")
+
+KNNJ_OK, KNNJ_EINVAL, KNNJ_ENOMEM, KNNJ_EDEVICE, KNNJ_EOVERFLOW, KNNJ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+KNNJ_U8, KNNJ_F32 = 0, 1
+KNNJ_IIB, KNNJ_IIIB = 0, 1
+KNNJ_FLAG_NO_VALIDATE = 1
+STAT_POSTINGS, STAT_COMPLETION, STAT_CANDIDATES, STAT_FALLBACKS, STAT_COUNT = 0, 1, 2, 3, 8
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "EUNSUPPORTED"}
+
+
+class KnnjError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("knnj %s: %s" % (_STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_dims", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("values", ctypes.c_void_p)]
+
+
+class _IndexOpts(ctypes.Structure):
+    _fields_ = [("tile_width", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class _JoinOpts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("flags", ctypes.c_uint32), ("r_block_rows", ctypes.c_int64),
+                ("theta_seed", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("fallback_out", ctypes.c_void_p),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class _IndexInfo(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_dims", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("tile_width", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("max_row_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libknnj.so and declare its C signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libknnj.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.knnj_build_index.argtypes = [ctypes.POINTER(_CSR), ctypes.POINTER(_IndexOpts), P, ctypes.POINTER(P)]
+    lib.knnj_build_index.restype = I32
+    lib.knnj_index_info_get.argtypes = [P, ctypes.POINTER(_IndexInfo)]
+    lib.knnj_index_info_get.restype = I32
+    lib.knnj_index_list_lengths.argtypes = [P, P, P]
+    lib.knnj_index_list_lengths.restype = I32
+    lib.knnj_index_free.argtypes = [P]
+    lib.knnj_index_free.restype = None
+    lib.knnj_join.argtypes = [P, ctypes.POINTER(_CSR), I32, ctypes.POINTER(_JoinOpts), P, P, P, P]
+    lib.knnj_join.restype = I32
+    lib.knnj_join_bf.argtypes = [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), I32, P, P, P, P]
+    lib.knnj_join_bf.restype = I32
+    lib.knnj_last_error.argtypes = []
+    lib.knnj_last_error.restype = ctypes.c_char_p
+    del I64
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != KNNJ_OK:
+        raise KnnjError(rc, _lib.knnj_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix in device memory (torch tensors)."""
+    indptr: torch.Tensor   # int64[n+1]
+    indices: torch.Tensor  # int32[nnz]
+    values: torch.Tensor   # uint8 or float32[nnz]
+    n_dims: int
+
+    @staticmethod
+    def from_host(m, device="cuda") -> "DeviceCSR":
+        """Copy a host CSR (numpy arrays indptr/indices/values, attribute n_dims)."""
+        return DeviceCSR(torch.from_numpy(np.ascontiguousarray(m.indptr, dtype=np.int64)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(m.indices, dtype=np.int32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(m.values)).to(device), int(m.n_dims))
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.indptr.shape[0]) - 1
+
+    @property
+    def dtype(self) -> int:
+        return KNNJ_U8 if self.values.dtype == torch.uint8 else KNNJ_F32
+
+    def _c(self) -> _CSR:
+        for t, dt in ((self.indptr, torch.int64), (self.indices, torch.int32)):
+            if t.dtype != dt or not t.is_contiguous() or t.device.type != "cuda":
+                raise TypeError("CSR arrays must be contiguous device tensors (indptr int64, indices int32)")
+        if self.values.dtype not in (torch.uint8, torch.float32) or not self.values.is_contiguous():
+            raise TypeError("CSR values must be a contiguous uint8 or float32 device tensor")
+        return _CSR(self.n_rows, self.n_dims, self.dtype, int(self.indices.shape[0]), _ptr(self.indptr),
+                    _ptr(self.indices), _ptr(self.values))
+
+
+class Index:
+    """Inverted index of S (owned by the library; freed with the object)."""
+
+    def __init__(self, handle: ctypes.c_void_p, S: DeviceCSR):
+        self._h = handle
+        self.n_dims = S.n_dims
+        self.dtype = S.dtype
+        info = _IndexInfo()
+        _check(_lib.knnj_index_info_get(self._h, ctypes.byref(info)))
+        self.info = info
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.info.n_rows)
+
+    @property
+    def tile_width(self) -> int:
+        return int(self.info.tile_width)
+
+    @property
+    def n_tiles(self) -> int:
+        return int(self.info.n_tiles)
+
+    def list_lengths(self, stream=None) -> torch.Tensor:
+        """|I_d| for every dimension (device int32)."""
+        out = torch.empty(self.n_dims, dtype=torch.int32, device="cuda")
+        _check(_lib.knnj_index_list_lengths(self._h, _ptr(out), _stream(stream)))
+        return out
+
+    def free(self):
+        if self._h is not None and _lib is not None:
+            _lib.knnj_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_index(S: DeviceCSR, tile_width: int = 0, stream=None) -> Index:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    opts = _IndexOpts(int(tile_width))
+    c = S._c()
+    _check(lib.knnj_build_index(ctypes.byref(c), ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
+    return Index(h, S)
+
+
+def _outputs(n: int, k: int, dtype: int, out):
+    if out is not None:
+        return out
+    sdt = torch.int32 if dtype == KNNJ_U8 else torch.float32
+    return (torch.empty((n, k), dtype=torch.int32, device="cuda"), torch.empty((n, k), dtype=sdt, device="cuda"),
+            torch.empty(n, dtype=torch.int32, device="cuda"))
+
+
+def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows: int = 0,
+             theta_seed: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
+             fallback_out: Optional[torch.Tensor] = None, validate: bool = True, out=None, stream=None):
+    """Exact top-k of every row of R against the indexed S.
+
+    Returns (ids int32[n,k], scores int32|float32[n,k], count int32[n]) on the device.
+    algo: "iib" or "iiib".  theta_seed: optional float32[n] device tensor of
+    k-th score guesses (IIIB).  stats: optional int64[8] device tensor of
+    counters (added to).  fallback_out: optional uint8[n] device tensor.
+    """
+    lib = load_library()
+    ids, sc, cnt = _outputs(R.n_rows, k, index.dtype, out)
+    o = _JoinOpts()
+    o.algo = KNNJ_IIIB if algo == "iiib" else KNNJ_IIB
+    o.flags = 0 if validate else KNNJ_FLAG_NO_VALIDATE
+    o.r_block_rows = int(r_block_rows)
+    if theta_seed is not None:
+        assert theta_seed.dtype == torch.float32 and theta_seed.is_cuda and theta_seed.numel() == R.n_rows
+    if stats is not None:
+        assert stats.dtype == torch.int64 and stats.is_cuda and stats.numel() >= STAT_COUNT
+    o.theta_seed = _ptr(theta_seed)
+    o.stats = _ptr(stats)
+    o.fallback_out = _ptr(fallback_out)
+    c = R._c()
+    _check(lib.knnj_join(index._h, ctypes.byref(c), int(k), ctypes.byref(o), _ptr(ids), _ptr(sc), _ptr(cnt),
+                         _stream(stream)))
+    return ids, sc, cnt
+
+
+def knn_join_bf(S: DeviceCSR, R: DeviceCSR, k: int, out=None, stream=None):
+    """Brute-force join (Algorithm 2); same outputs as knn_join."""
+    lib = load_library()
+    ids, sc, cnt = _outputs(R.n_rows, k, S.dtype, out)
+    cs, cr = S._c(), R._c()
+    _check(lib.knnj_join_bf(ctypes.byref(cs), ctypes.byref(cr), int(k), _ptr(ids), _ptr(sc), _ptr(cnt),
+                            _stream(stream)))
+    return ids, sc, cnt
