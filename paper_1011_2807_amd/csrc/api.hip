@@ -25,7 +25,6 @@ knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join
                         int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st);
-knnj_status set_smem_limits(int max_smem);
 size_t tile_smem_bytes(int tile);
 
 static knnj_status check_csr_host(const knnj_csr* m, const char* name) {
@@ -85,7 +84,7 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
   *out = nullptr;
   knnj_status rc = check_csr_host(S, "S");
   if (rc != KNNJ_OK) return rc;
-  int tile = opt && opt->tile_width ? opt->tile_width : 8192;
+  int tile = opt && opt->tile_width ? opt->tile_width : 4096;
   if (tile < 256 || tile > 65536 || (tile & (tile - 1)))
     return fail(KNNJ_EINVAL, "tile_width must be a power of two in [256, 65536]");
   hipStream_t st = (hipStream_t)stream;
@@ -95,7 +94,6 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
   if (tile_smem_bytes(tile) > size_t(max_smem))
     return fail(KNNJ_EUNSUPPORTED, "tile_width too large for this device's local memory (" +
                                        std::to_string(max_smem) + " bytes per workgroup)");
-  if ((rc = set_smem_limits(max_smem)) != KNNJ_OK) return rc;
   Index* ix = new Index();
   ix->device = dev;
   ix->n_rows = S->n_rows;

@@ -296,10 +296,4 @@ knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* 
   return KNNJ_OK;
 }
 
-knnj_status set_smem_limits(int max_smem) {
-  KNNJ_HIP(hipFuncSetAttribute((const void*)k_iib_tile<uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
-  KNNJ_HIP(hipFuncSetAttribute((const void*)k_iib_tile<float>, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
-  return KNNJ_OK;
-}
-
 }  // namespace knnj
