@@ -121,12 +121,18 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
   if (hipMalloc(&ix->s_indptr, sizeof(int64_t) * (S->n_rows + 1)) != hipSuccess ||
       hipMalloc(&ix->s_indices, sizeof(int32_t) * nnz1) != hipSuccess ||
       hipMalloc(&ix->s_values, vbytes * nnz1) != hipSuccess ||
-      (S->dtype == KNNJ_U8 ? hipMalloc(&ix->post_u8, sizeof(uint32_t) * nnz1)
-                           : (hipMalloc(&ix->post_s, sizeof(uint16_t) * nnz1) == hipSuccess
-                                  ? hipMalloc(&ix->post_w, sizeof(float) * nnz1)
+      (S->dtype == KNNJ_U8 ? hipMalloc(&ix->post_u8, sizeof(uint32_t) * (nnz1 + kPostPad))
+                           : (hipMalloc(&ix->post_s, sizeof(uint16_t) * (nnz1 + kPostPad)) == hipSuccess
+                                  ? hipMalloc(&ix->post_w, sizeof(float) * (nnz1 + kPostPad))
                                   : hipErrorOutOfMemory)) != hipSuccess) {
     free_index(ix);
     return fail(KNNJ_ENOMEM, "device allocation for the index failed");
+  }
+  if ((S->dtype == KNNJ_U8 ? hipMemsetAsync(ix->post_u8 + nnz1, 0, sizeof(uint32_t) * kPostPad, st)
+                           : hipMemsetAsync(ix->post_s + nnz1, 0, sizeof(uint16_t) * kPostPad, st)) != hipSuccess ||
+      (S->dtype == KNNJ_F32 && hipMemsetAsync(ix->post_w + nnz1, 0, sizeof(float) * kPostPad, st) != hipSuccess)) {
+    free_index(ix);
+    return fail(KNNJ_EDEVICE, "hipMemsetAsync failed");
   }
   if (hipMemcpyAsync(ix->s_indptr, S->indptr, sizeof(int64_t) * (S->n_rows + 1), hipMemcpyDeviceToDevice, st) !=
           hipSuccess ||

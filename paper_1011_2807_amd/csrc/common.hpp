@@ -13,8 +13,8 @@ namespace knnj {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;           // threads per workgroup for most kernels
 constexpr int kMaxK = 1024;           // largest k accepted by the join
-constexpr int kSortBuf = 2048;        // selection buffer entries (>= 2 * kMaxK)
-constexpr int kSegChunk = 512;        // query features staged per pass of the postings walk
+constexpr int kSegChunk = kBlock;     // query features staged per pass of the postings walk
+constexpr int kPostPad = 8;           // zeroed entries after the postings (vector loads past the end)
 constexpr int kMaxRowNnz = 4096;      // longest row accepted
 constexpr int kLevels = 64;           // IIIB threshold levels
 

@@ -18,11 +18,20 @@ namespace knnj {
 
 // Local-memory workspace of the selection (reuses the walk's staging area).
 struct SelectSmem {
-  uint64_t* keys;  // kSortBuf
+  uint64_t* keys;  // cap entries
+  uint32_t cap;    // power of two >= 2k
   uint32_t* hist;  // 256
   uint32_t* scal;  // 8
   uint32_t* tmp;   // kBlock / kWave + 1
 };
+
+// Selection buffer entries for a given k: a power of two >= max(256, 2k).
+__host__ __device__ inline uint32_t select_cap(int k) {
+  uint32_t c = 256;
+  while (c < uint32_t(2 * k)) c <<= 1;
+  return c;
+}
+__host__ __device__ inline uint32_t select_bytes(int k) { return select_cap(k) * 8u + 256u * 4u + 8u * 4u; }
 
 __device__ __forceinline__ uint32_t to_bits(uint32_t v) { return v; }
 __device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
@@ -109,7 +118,7 @@ __device__ void tile_select(const S* acc, int n_valid, int64_t s_base, int k, in
   // candidate rule: bits > lo_bits, or (with ties) bits > tie_v || (bits == tie_v && i <= tie_u)
   uint32_t lo_bits = theta, tie_v = 0, tie_u = 0;
   bool use_tie = false;
-  if (n + uint32_t(cnt) > uint32_t(kSortBuf)) {
+  if (n + uint32_t(cnt) > sm.cap) {
     auto val = [&](int i) { return to_bits(acc[i]); };
     auto pred = [&](int i) { return to_bits(acc[i]) > theta; };
     const uint32_t v = radix_select<32>(n_valid, uint32_t(k), true, val, pred, sm);
@@ -121,7 +130,7 @@ __device__ void tile_select(const S* acc, int n_valid, int64_t s_base, int k, in
     }
     g = block_sum(g, sm.tmp);
     e = block_sum(e, sm.tmp);
-    if (g + e + uint32_t(cnt) <= uint32_t(kSortBuf)) {
+    if (g + e + uint32_t(cnt) <= sm.cap) {
       lo_bits = v - 1u;  // v > theta >= 0
     } else {
       // too many equal scores: keep the (k - g) lowest ids among them
