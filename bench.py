@@ -37,6 +37,8 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--algo", default="iib", choices=["iib", "iiib"])
+    ap.add_argument("--bound", action="store_true", help="IIIB: bound-filtered completion")
+    ap.add_argument("--drop", type=int, default=0, help="IIIB: level drop")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--n-r", type=int, default=0, help="override |R| (quick runs only)")
@@ -118,7 +120,8 @@ def main():
     stats = torch.zeros(8, dtype=torch.int64, device=dev)
     # warmup (validated), also fills the counters
     for w in range(max(1, a.warmup)):
-        kj.knn_join(ix, dR, k, algo=a.algo, stats=stats if w == 0 else None, validate=(w == 0), out=out)
+        kj.knn_join(ix, dR, k, algo=a.algo, stats=stats if w == 0 else None, validate=(w == 0), out=out,
+                    bound_filter=a.bound, level_drop=a.drop)
         torch.cuda.synchronize()
         print("warmup %d done" % w, file=sys.stderr, flush=True)
     walked = int(stats[kj.STAT_POSTINGS].item())
@@ -128,7 +131,8 @@ def main():
     t_wall = time.time()
     ev0.record(stream)
     for s in range(a.steps):
-        kj.knn_join(ix, dR, k, algo=a.algo, validate=False, out=out, stream=stream)
+        kj.knn_join(ix, dR, k, algo=a.algo, validate=False, out=out, stream=stream, bound_filter=a.bound,
+                    level_drop=a.drop)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.time() - t_wall
@@ -176,8 +180,10 @@ def main():
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8" if sdt == torch.int32 else "f32", "data": "synthetic",
-        "config": {"workload": a.workload, "algo": a.algo, "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
+        "config": {"workload": a.workload, "algo": a.algo, "bound_filter": a.bound, "level_drop": a.drop, "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
                    "tile_width": ix.tile_width, "nnz_s": S.nnz, "nnz_r": R.nnz},
+        "iiib_counters": {"completion_entries": int(stats[kj.STAT_COMPLETION].item()),
+                          "candidates": int(stats[kj.STAT_CANDIDATES].item())} if a.algo == "iiib" else None,
         "postings_entries_per_s": eps, "postings_GBps": round(gbps, 1), "postings_entries_per_step": walked,
         "index_build_s": round(t_build, 3), "oracle_spot_check": {"queries": len(rows), "exact": ok},
         "roofline": roof, "cpu_baseline": cpu,

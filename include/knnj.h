@@ -89,6 +89,10 @@ typedef struct {
 
 /* Flags of knnj_join_opts.flags */
 #define KNNJ_FLAG_NO_VALIDATE 1u /* skip the device check of R's CSR structure (no host sync) */
+/* IIIB only, beyond the paper (its Sec. 6 asks for stronger refinement): skip the
+ * completion of an s whose indexed partial score A[s] plus the bound of its
+ * unindexed part cannot reach the threshold.  Results stay exact. */
+#define KNNJ_FLAG_IIIB_BOUND 2u
 
 /* Counters accumulated into knnj_join_opts.stats (device uint64[KNNJ_STAT_COUNT]). */
 enum {
@@ -115,7 +119,12 @@ typedef struct {
   uint64_t* stats;
   /* Optional device uint8[n_rows of R]: set to 1 for queries that fell back. */
   uint8_t* fallback_out;
-  int32_t reserved[6];
+  /* IIIB: index features whose bound reaches a ladder step this many steps
+   * (factors of 2^(1/4)) below the threshold; 0 = the step at the threshold.
+   * Any value keeps the result exact; it trades indexed postings for
+   * completion work.  In [0, 63]. */
+  int32_t level_drop;
+  int32_t reserved[5];
 } knnj_join_opts;
 
 /*

@@ -50,17 +50,14 @@ struct Index {
   int64_t* s_indptr = nullptr;
   int32_t* s_indices = nullptr;
   void* s_values = nullptr;
-  // IIIB per-R-block index (rebuilt per block, grow-only buffers)
-  size_t iiib_cap_entries = 0;
-  uint32_t* iiib_post = nullptr;     // entries (s_local << 16) | (w << 8) | level
-  float* iiib_post_w = nullptr;      // f32 weights, same order
+  // IIIB index of the current R block (rebuilt per block, allocated on first use)
+  uint32_t* iiib_post = nullptr;     // u8 entries (s_local << 16) | (w << 8) | level, lists in level-desc order
   uint16_t* iiib_post_s = nullptr;   // f32 s_local, same order
-  uint32_t* iiib_fwd = nullptr;      // per S row, features in the block's order: (d << 14 ... ) see iiib.hip
-  float* iiib_fwd_w = nullptr;
-  uint16_t* iiib_cut = nullptr;      // per (tile, d, level): entries with level >= that level
-  size_t iiib_cut_cap = 0;
+  float* iiib_post_w = nullptr;      // f32 weights, same order
+  uint32_t* iiib_fwd = nullptr;      // each S row in the block's dimension order (see iiib.hip)
+  float* iiib_fwd_w = nullptr;       // f32 weights of iiib_fwd
+  uint32_t* iiib_cut = nullptr;      // [(tile, d), level]: entries of list (tile, d) with level >= that level
   uint64_t* rec_tmp = nullptr;       // build scratch (8 bytes per entry)
-  size_t rec_cap = 0;
   // small persistent scratch
   int32_t* dev_err = nullptr;        // validation result
   uint64_t* stat_slots = nullptr;    // spread counters, reduced into caller stats

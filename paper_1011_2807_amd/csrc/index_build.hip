@@ -359,7 +359,6 @@ knnj_status build_postings(Index* ix, const int64_t* indptr, const int32_t* indi
     cleanup();
     return fail(KNNJ_ENOMEM, "device allocation for the index failed");
   }
-  ix->rec_cap = size_t(ix->nnz > 0 ? ix->nnz : 1);
   do {
     if (hipMemsetAsync(cnt, 0, sizeof(uint32_t) * n_keys, st) != hipSuccess ||
         hipMemsetAsync(cursor, 0, sizeof(uint32_t) * n_keys, st) != hipSuccess ||

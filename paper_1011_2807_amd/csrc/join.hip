@@ -5,13 +5,14 @@
 // line 10) is a dense array acc[T] in local memory indexed by s_local; the
 // postings walk adds r[d] * w to acc[s_local] with local-memory atomics, which
 // are exact for integer scores.  The lists (t, d) of all features of r are
-// walked as one concatenated sequence so that every lane of the workgroup has
-// work even when the lists are short: lane i handles positions
-// i, i + 256, i + 512, ... of the concatenation and carries the index of the
-// list it is in, so each position costs one compare and one load.
-#include "select.hpp"
+// walked as one concatenated sequence of 16-byte groups shared out over teams of
+// lanes (see walk_lists), so lanes stay busy even when most lists are short.
+#include "walk.hpp"
 
 namespace knnj {
+
+size_t tile_smem_bytes(int tile, int k) { return size_t(tile) * 4 + stage_bytes(k); }
+size_t tile_smem_bytes(int tile) { return tile_smem_bytes(tile, kMaxK); }
 
 __global__ void k_init_out(int64_t n, int32_t* ids, uint32_t* sc, int64_t n_rows, int32_t* cnt) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -36,142 +37,6 @@ __global__ void k_reduce_stats(const uint64_t* slots, int n_slots, uint64_t* out
   if (threadIdx.x == 0 && part[0] != 0) atomicAdd((unsigned long long*)&out[blockIdx.x], (unsigned long long)part[0]);
 }
 
-// Dynamic local memory of the tile kernels: [acc: T scores][stage], where the
-// stage holds either the walk's list table or the selection workspace.
-//   list table (kSegChunk lists): pre uint32[kSegChunk + 2] | cbase int64[kSegChunk]
-//                                 | meta uint32[kSegChunk] | w 4-byte[kSegChunk]
-constexpr int kPreOff = 0;
-constexpr int kCbOff = 4 * (kSegChunk + 2);
-constexpr int kMetaOff = kCbOff + 8 * kSegChunk;
-constexpr int kWOff = kMetaOff + 4 * kSegChunk;
-constexpr int kWalkBytes = kWOff + 4 * kSegChunk;
-
-size_t stage_bytes(int k) {
-  const size_t sel = select_bytes(k);
-  return sel > size_t(kWalkBytes) ? sel : size_t(kWalkBytes);
-}
-size_t tile_smem_bytes(int tile, int k) { return size_t(tile) * 4 + stage_bytes(k); }
-size_t tile_smem_bytes(int tile) { return tile_smem_bytes(tile, kMaxK); }
-
-__device__ __forceinline__ SelectSmem select_smem(char* stage, int k, uint32_t* tmp) {
-  const uint32_t cap = select_cap(k);
-  return SelectSmem{reinterpret_cast<uint64_t*>(stage), cap, reinterpret_cast<uint32_t*>(stage + 8 * cap),
-                    reinterpret_cast<uint32_t*>(stage + 8 * cap + 1024), tmp};
-}
-
-template <typename V>
-struct Postings;
-// u8: entries (s_local << 16) | (w << 8), read four at a time (16-byte aligned groups)
-template <>
-struct Postings<uint8_t> {
-  const uint4* e;
-};
-// f32: s_local uint16 and weight float arrays, four at a time
-template <>
-struct Postings<float> {
-  const uint2* s;
-  const float4* w;
-};
-
-// Stage the lists (tile, d) of features [cb, cb + n) of one query; returns the
-// number of 4-entry groups in their concatenation.  Thread t stages list t.
-template <typename V, typename S>
-__device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int64_t key0, const int32_t* r_idx,
-                                                const V* r_val, int64_t cb, int n, const int64_t* offsets) {
-  uint32_t* pre = reinterpret_cast<uint32_t*>(stage + kPreOff);
-  int64_t* cbase = reinterpret_cast<int64_t*>(stage + kCbOff);
-  uint32_t* meta = reinterpret_cast<uint32_t*>(stage + kMetaOff);
-  S* w_of = reinterpret_cast<S*>(stage + kWOff);
-  const int j = threadIdx.x;
-  uint32_t groups = 0, len = 0, off = 0;
-  int64_t beg = 0;
-  S w = S(0);
-  if (j < n) {
-    const int64_t key = key0 + r_idx[cb + j];
-    beg = offsets[key];
-    len = uint32_t(offsets[key + 1] - beg);
-    off = uint32_t(beg & 3);
-    groups = len ? uint32_t(((beg + len + 3) >> 2) - (beg >> 2)) : 0u;
-    w = S(r_val[cb + j]);
-  }
-  uint32_t total;
-  const uint32_t ex = block_exclusive_scan(groups, tmp, &total);
-  if (j < n) {
-    pre[j] = ex;
-    cbase[j] = (beg >> 2) - int64_t(ex);
-    meta[j] = (len << 2) | off;
-    w_of[j] = w;
-  }
-  if (j == 0) pre[n] = total;
-  __syncthreads();
-  return total;
-}
-
-// Walk the staged concatenation: lane i takes groups i, i + 256, ...; a group
-// is one aligned 16-byte load of four entries, of which those inside the
-// list's range are added into acc with local-memory atomics.
-template <typename V, typename S>
-__device__ __forceinline__ void walk_lists(S* acc, const char* stage, uint32_t total, Postings<V> P) {
-  constexpr int U = 4;
-  const uint32_t* pre = reinterpret_cast<const uint32_t*>(stage + kPreOff);
-  const int64_t* cbase = reinterpret_cast<const int64_t*>(stage + kCbOff);
-  const uint32_t* meta = reinterpret_cast<const uint32_t*>(stage + kMetaOff);
-  const S* w_of = reinterpret_cast<const S*>(stage + kWOff);
-  int j = 0;
-  uint32_t cur = 0, nxt = pre[1];
-  int64_t cb = cbase[0];
-  uint32_t mt = meta[0];
-  S w = w_of[0];
-  for (uint32_t g0 = threadIdx.x; g0 < total; g0 += kBlock * U) {
-    uint4 e[U];
-    uint2 es[U];
-    float4 ew[U];
-    uint32_t rel[U], len[U];
-    S ww[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t g = g0 + u * kBlock;
-      len[u] = 0;
-      if (g < total) {
-        if (g >= nxt) {
-          do {
-            ++j;
-            nxt = pre[j + 1];
-          } while (g >= nxt);
-          cur = pre[j];
-          cb = cbase[j];
-          mt = meta[j];
-          w = w_of[j];
-        }
-        if constexpr (sizeof(V) == 1) {
-          e[u] = P.e[cb + g];
-        } else {
-          es[u] = P.s[cb + g];
-          ew[u] = P.w[cb + g];
-        }
-        rel[u] = 4u * (g - cur) - (mt & 3u);
-        len[u] = mt >> 2;
-        ww[u] = w;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if constexpr (sizeof(V) == 1) {
-        const uint32_t x[4] = {e[u].x, e[u].y, e[u].z, e[u].w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[x[i] >> 16], ww[u] * ((x[i] >> 8) & 0xffu));
-      } else {
-        const uint32_t sx[4] = {es[u].x & 0xffffu, es[u].x >> 16, es[u].y & 0xffffu, es[u].y >> 16};
-        const float wx[4] = {ew[u].x, ew[u].y, ew[u].z, ew[u].w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[sx[i]], ww[u] * wx[i]);
-      }
-    }
-  }
-}
-
 // IIB on tile `tile` for queries q0 + blockIdx.x.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_tile, int64_t n_s, int32_t n_dims,
@@ -190,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_
 
   const int64_t q = q0 + blockIdx.x;
   const int64_t s_base = int64_t(tile) << log2_tile;
-  const int n_valid = int(n_s - s_base < T ? n_s - s_base : T);
+  (void)n_s;  // rows past the end of S have no postings, so their slots stay 0
   for (int i = threadIdx.x; i < T / 4; i += kBlock) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
 
   const int64_t rb = r_ptr[q], re = r_ptr[q + 1];
@@ -199,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_
   for (int64_t cb = rb; cb < re; cb += kSegChunk) {
     const int n = int(re - cb < kSegChunk ? re - cb : kSegChunk);
     const uint32_t total = stage_lists<V, S>(stage, tmp, key0, r_idx, r_val, cb, n, offsets);
-    walk_lists<V, S>(acc, stage, total, P);
+    walk_lists<V, S>(acc, stage, n, total, P);
     if (slots) {
       // exact entries walked: sum of list lengths of this pass
       uint32_t l = threadIdx.x < n ? reinterpret_cast<const uint32_t*>(stage + kMetaOff)[threadIdx.x] >> 2 : 0u;
@@ -207,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_
     }
     __syncthreads();
   }
-  tile_select<S>(acc, n_valid, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q, select_smem(stage, k, tmp));
+  tile_select<S, true>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q, select_smem(stage, k, tmp));
   if (threadIdx.x == 0 && slots) atomicAdd((unsigned long long*)&slots[KNNJ_STAT_POSTINGS * 256 + (blockIdx.x & 255)],
                                            (unsigned long long)walked);
 }
@@ -261,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_bf(int32_t log2_tile, int64_t n_s, i
       acc[i] = ret;
     }
     __syncthreads();
-    tile_select<S>(acc, n_valid, s0, k, out_ids + q * k, out_sc + q * k, out_cnt + q, sm);
+    tile_select<S, false>(acc, n_valid, s0, k, out_ids + q * k, out_sc + q * k, out_cnt + q, sm);
     __syncthreads();
   }
 }

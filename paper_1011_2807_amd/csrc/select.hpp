@@ -103,9 +103,15 @@ __device__ uint32_t radix_select(int n, uint32_t want, bool desc, ValF val, Pred
   return prefix;
 }
 
-// acc[0..n_valid): scores of S rows s_base + i.  The running list of this
-// query lives in o_ids / o_sc (k slots) and *o_cnt.
-template <typename S>
+// Slot of row s_local in a swizzled score array: the low five address bits are
+// XORed with the next five, so lanes that touch rows a fixed stride apart (4 to
+// 32 rows) land in different LDS banks.  The map is its own inverse.
+__device__ __forceinline__ uint32_t swz(uint32_t s) { return s ^ ((s >> 5) & 31u); }
+
+// acc[0..n): scores; slot i holds row s_base + (SWZ ? swz(i) : i), rows past the
+// tile's end hold 0.  The running list of this query lives in o_ids / o_sc
+// (k slots) and *o_cnt.
+template <typename S, bool SWZ>
 __device__ void tile_select(const S* acc, int n_valid, int64_t s_base, int k, int32_t* __restrict__ o_ids,
                             S* __restrict__ o_sc, int32_t* __restrict__ o_cnt, const SelectSmem& sm) {
   const int cnt = *o_cnt;
@@ -134,7 +140,7 @@ __device__ void tile_select(const S* acc, int n_valid, int64_t s_base, int k, in
       lo_bits = v - 1u;  // v > theta >= 0
     } else {
       // too many equal scores: keep the (k - g) lowest ids among them
-      auto ival = [&](int i) { return uint32_t(i); };
+      auto ival = [&](int i) { return SWZ ? swz(uint32_t(i)) : uint32_t(i); };
       auto ipred = [&](int i) { return to_bits(acc[i]) == v; };
       tie_u = radix_select<16>(n_valid, uint32_t(k) - g, false, ival, ipred, sm);
       tie_v = v;
@@ -147,10 +153,11 @@ __device__ void tile_select(const S* acc, int n_valid, int64_t s_base, int k, in
   __syncthreads();
   for (int i = threadIdx.x; i < n_valid; i += kBlock) {
     const uint32_t b = to_bits(acc[i]);
-    const bool take = use_tie ? (b > tie_v || (b == tie_v && uint32_t(i) <= tie_u)) : (b > lo_bits);
+    const uint32_t sl = SWZ ? swz(uint32_t(i)) : uint32_t(i);
+    const bool take = use_tie ? (b > tie_v || (b == tie_v && sl <= tie_u)) : (b > lo_bits);
     if (take) {
       const uint32_t pos = atomicAdd(&sm.scal[2], 1u);
-      sm.keys[pos] = (uint64_t(b) << 32) | uint32_t(~uint32_t(s_base + i));
+      sm.keys[pos] = (uint64_t(b) << 32) | uint32_t(~uint32_t(s_base + sl));
     }
   }
   __syncthreads();

@@ -21,6 +21,7 @@ KNNJ_OK, KNNJ_EINVAL, KNNJ_ENOMEM, KNNJ_EDEVICE, KNNJ_EOVERFLOW, KNNJ_EUNSUPPORT
 KNNJ_U8, KNNJ_F32 = 0, 1
 KNNJ_IIB, KNNJ_IIIB = 0, 1
 KNNJ_FLAG_NO_VALIDATE = 1
+KNNJ_FLAG_IIIB_BOUND = 2
 STAT_POSTINGS, STAT_COMPLETION, STAT_CANDIDATES, STAT_FALLBACKS, STAT_COUNT = 0, 1, 2, 3, 8
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "EUNSUPPORTED"}
 
@@ -44,7 +45,7 @@ class _IndexOpts(ctypes.Structure):
 class _JoinOpts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("flags", ctypes.c_uint32), ("r_block_rows", ctypes.c_int64),
                 ("theta_seed", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("fallback_out", ctypes.c_void_p),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("level_drop", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class _IndexInfo(ctypes.Structure):
@@ -192,19 +193,22 @@ def _outputs(n: int, k: int, dtype: int, out):
 
 def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows: int = 0,
              theta_seed: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
-             fallback_out: Optional[torch.Tensor] = None, validate: bool = True, out=None, stream=None):
+             fallback_out: Optional[torch.Tensor] = None, validate: bool = True, bound_filter: bool = False,
+             level_drop: int = 0, out=None, stream=None):
     """Exact top-k of every row of R against the indexed S.
 
     Returns (ids int32[n,k], scores int32|float32[n,k], count int32[n]) on the device.
     algo: "iib" or "iiib".  theta_seed: optional float32[n] device tensor of
     k-th score guesses (IIIB).  stats: optional int64[8] device tensor of
     counters (added to).  fallback_out: optional uint8[n] device tensor.
+    bound_filter / level_drop: IIIB refinements (see knnj.h); results stay exact.
     """
     lib = load_library()
     ids, sc, cnt = _outputs(R.n_rows, k, index.dtype, out)
     o = _JoinOpts()
     o.algo = KNNJ_IIIB if algo == "iiib" else KNNJ_IIB
-    o.flags = 0 if validate else KNNJ_FLAG_NO_VALIDATE
+    o.flags = (0 if validate else KNNJ_FLAG_NO_VALIDATE) | (KNNJ_FLAG_IIIB_BOUND if bound_filter else 0)
+    o.level_drop = int(level_drop)
     o.r_block_rows = int(r_block_rows)
     if theta_seed is not None:
         assert theta_seed.dtype == torch.float32 and theta_seed.is_cuda and theta_seed.numel() == R.n_rows
