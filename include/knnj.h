@@ -179,6 +179,59 @@ knnj_status knnj_join(const knnj_index* ix, const knnj_csr* R, int32_t k, const 
 knnj_status knnj_join_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* out_ids, void* out_scores,
                          int32_t* out_count, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned threshold seed (not in the paper; its Sec. 6 asks for stronger
+ * refinement).  A 64-128-128-1 MLP (ReLU, bfloat16 weights, float32
+ * accumulation) predicts a query's k-th score from 64 features; the prediction
+ * is passed to knnj_join as theta_seed.  Correctness never depends on it: the
+ * join's survivor check recomputes any query whose seed was too high.
+ * ------------------------------------------------------------------------ */
+typedef struct knnj_mlp knnj_mlp;
+
+#define KNNJ_MLP_FEATURES 64
+#define KNNJ_MLP_PARAMS 24961 /* W1[128][64] b1[128] W2[128][128] b2[128] w3[128] b3 */
+#define KNNJ_MLP_NORM 129     /* feature mean[64], feature std[64], label scale */
+
+typedef struct {
+  int32_t epochs;  /* passes over the training set, >= 1 */
+  int32_t batch;   /* minibatch size in [1, 65536] */
+  float lr;        /* Adam step size */
+  float tau;       /* pinball-loss quantile in (0, 1); small values bias the seed low */
+  uint64_t seed;   /* shuffling seed */
+  int32_t reserved[8];
+} knnj_train_opts;
+
+/* New network with He-uniform weights drawn from `seed` (host RNG), zero
+ * biases, identity normalisation.  Errors: EINVAL, ENOMEM, EDEVICE. */
+knnj_status knnj_mlp_create(uint64_t seed, knnj_mlp** out);
+void knnj_mlp_free(knnj_mlp* m);
+
+/* Features of every row of R (device float[n_rows][64]): log(1 + nnz), the
+ * share of features in each of 16 weight bins, and the share in each of 47
+ * bins of floor(2 log2(1 + |I_d|)) (list lengths from the index). */
+knnj_status knnj_mlp_features(const knnj_index* ix, const knnj_csr* R, float* out, void* stream);
+
+/* Train on n samples: X device float[n][64], y device float[n] (exact k-th
+ * scores).  Sets the normalisation from X and y, then runs minibatch Adam on
+ * the pinball loss.  epoch_loss (host float[epochs], nullable) receives each
+ * epoch's mean batch loss.  Synchronises the stream. */
+knnj_status knnj_mlp_train(knnj_mlp* m, const float* X, const float* y, int64_t n, const knnj_train_opts* opt,
+                           float* epoch_loss, void* stream);
+
+/* theta_out (device float[n]) = predicted k-th score of each row of X. */
+knnj_status knnj_mlp_predict(const knnj_mlp* m, const float* X, int64_t n, float* theta_out, void* stream);
+
+/* Gradient of the mean pinball loss over the n samples at the current working
+ * weights, without updating them: grad_out device float[24961], loss_out device
+ * float[1].  Synchronises the stream. */
+knnj_status knnj_mlp_grad(knnj_mlp* m, const float* X, const float* y, int64_t n, float tau, float* grad_out,
+                          float* loss_out, void* stream);
+
+/* Host copies of the working (bfloat16-rounded) weights and the normalisation;
+ * set_state rounds the given weights to bfloat16 for the working copy. */
+knnj_status knnj_mlp_get_state(const knnj_mlp* m, float* params, float* norm);
+knnj_status knnj_mlp_set_state(knnj_mlp* m, const float* params, const float* norm);
+
 /* Thread-local description of the last failure ("" if none). */
 const char* knnj_last_error(void);
 

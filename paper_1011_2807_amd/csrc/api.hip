@@ -71,6 +71,10 @@ static void free_index(Index* ix) {
 
 using namespace knnj;
 
+namespace knnj {
+const uint32_t* index_list_len(const knnj_index* h) { return reinterpret_cast<const Index*>(h)->list_len; }
+}  // namespace knnj
+
 // The public handle is the internal Index itself, seen through an opaque type.
 static Index* impl(const knnj_index* h) { return reinterpret_cast<Index*>(const_cast<knnj_index*>(h)); }
 

@@ -231,3 +231,100 @@ def knn_join_bf(S: DeviceCSR, R: DeviceCSR, k: int, out=None, stream=None):
     _check(lib.knnj_join_bf(ctypes.byref(cs), ctypes.byref(cr), int(k), _ptr(ids), _ptr(sc), _ptr(cnt),
                             _stream(stream)))
     return ids, sc, cnt
+
+
+# ---------------------------------------------------------------- learned seed
+MLP_FEATURES, MLP_PARAMS, MLP_NORM = 64, 24961, 129
+
+
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("tau", ctypes.c_float), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int32 * 8)]
+
+
+def _load_mlp(lib):
+    if getattr(lib, "_mlp_ready", False):
+        return lib
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.knnj_mlp_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(P)]
+    lib.knnj_mlp_create.restype = I32
+    lib.knnj_mlp_free.argtypes = [P]
+    lib.knnj_mlp_free.restype = None
+    lib.knnj_mlp_features.argtypes = [P, ctypes.POINTER(_CSR), P, P]
+    lib.knnj_mlp_features.restype = I32
+    lib.knnj_mlp_train.argtypes = [P, P, P, I64, ctypes.POINTER(_TrainOpts), P, P]
+    lib.knnj_mlp_train.restype = I32
+    lib.knnj_mlp_predict.argtypes = [P, P, I64, P, P]
+    lib.knnj_mlp_predict.restype = I32
+    lib.knnj_mlp_grad.argtypes = [P, P, P, I64, ctypes.c_float, P, P, P]
+    lib.knnj_mlp_grad.restype = I32
+    lib.knnj_mlp_get_state.argtypes = [P, P, P]
+    lib.knnj_mlp_get_state.restype = I32
+    lib.knnj_mlp_set_state.argtypes = [P, P, P]
+    lib.knnj_mlp_set_state.restype = I32
+    lib._mlp_ready = True
+    return lib
+
+
+class Mlp:
+    """Threshold-predicting MLP (64-128-128-1, bfloat16 weights) held by the library."""
+
+    def __init__(self, seed: int = 0):
+        self._lib = _load_mlp(load_library())
+        h = ctypes.c_void_p()
+        _check(self._lib.knnj_mlp_create(ctypes.c_uint64(seed), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def features(index: Index, R: DeviceCSR, stream=None) -> torch.Tensor:
+        lib = _load_mlp(load_library())
+        out = torch.empty((R.n_rows, MLP_FEATURES), dtype=torch.float32, device="cuda")
+        c = R._c()
+        _check(lib.knnj_mlp_features(index._h, ctypes.byref(c), _ptr(out), _stream(stream)))
+        return out
+
+    def train(self, X: torch.Tensor, y: torch.Tensor, epochs: int = 20, batch: int = 1024, lr: float = 1e-3,
+              tau: float = 0.05, seed: int = 0, stream=None):
+        assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous() and X.shape[1] == MLP_FEATURES
+        assert y.dtype == torch.float32 and y.is_cuda and y.numel() == X.shape[0]
+        o = _TrainOpts(int(epochs), int(batch), float(lr), float(tau), int(seed))
+        losses = (ctypes.c_float * int(epochs))()
+        _check(self._lib.knnj_mlp_train(self._h, _ptr(X), _ptr(y), int(X.shape[0]), ctypes.byref(o), losses,
+                                        _stream(stream)))
+        return list(losses)
+
+    def predict(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous() and X.shape[1] == MLP_FEATURES
+        out = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(self._lib.knnj_mlp_predict(self._h, _ptr(X), int(X.shape[0]), _ptr(out), _stream(stream)))
+        return out
+
+    def grad(self, X: torch.Tensor, y: torch.Tensor, tau: float, stream=None):
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(self._lib.knnj_mlp_grad(self._h, _ptr(X), _ptr(y), int(X.shape[0]), float(tau), _ptr(g), _ptr(loss),
+                                       _stream(stream)))
+        return g, loss
+
+    def get_state(self):
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        nrm = np.empty(MLP_NORM, dtype=np.float32)
+        _check(self._lib.knnj_mlp_get_state(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(nrm.ctypes.data)))
+        return p, nrm
+
+    def set_state(self, params: np.ndarray, norm: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nrm = np.ascontiguousarray(norm, dtype=np.float32)
+        assert p.shape == (MLP_PARAMS,) and nrm.shape == (MLP_NORM,)
+        _check(self._lib.knnj_mlp_set_state(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(nrm.ctypes.data)))
+
+    def free(self):
+        if self._h is not None:
+            self._lib.knnj_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
