@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
   // threshold: the running pruneScore, raised by the seed if one is given
   const int cnt = out_cnt[q];
   S theta = cnt == k ? out_sc[q * k + k - 1] : S(0);
-  if (seed && !qlist) {
+  if (seed) {
     const float sd = seed[q];
     if constexpr (sizeof(V) == 1) {
       // integer scores: a seed x means "score >= ceil(x)"
@@ -399,19 +399,22 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
 
 // Survivor check of a seeded pass: the result of q is exact iff it holds k
 // neighbours whose k-th score reaches the seed (every s scoring >= the seed was
-// found).  Other queries are reset and queued for a pass without the seed.
+// found).  Other queries are reset and queued for a second pass.  A queued query
+// that held k neighbours keeps their k-th score as its new seed: k real vectors
+// score at least that much, so it never exceeds the true k-th score and the
+// second pass needs no check.
 template <typename S>
 __global__ void k_survivors(int64_t q0, int64_t n, int32_t k, const float* __restrict__ seed,
-                            int32_t* __restrict__ ids, S* __restrict__ sc, int32_t* __restrict__ cnt,
-                            int32_t* __restrict__ qlist, uint32_t* __restrict__ qcount, uint8_t* __restrict__ fb_out,
-                            uint64_t* __restrict__ slots) {
+                            float* __restrict__ seed2, int32_t* __restrict__ ids, S* __restrict__ sc,
+                            int32_t* __restrict__ cnt, int32_t* __restrict__ qlist, uint32_t* __restrict__ qcount,
+                            uint8_t* __restrict__ fb_out, uint64_t* __restrict__ slots) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t q = q0 + i;
   const float sd = seed[q];
+  const int c = cnt[q];
   bool fb = false;
   if (sd > 0.0f) {
-    const int c = cnt[q];
     if constexpr (std::is_integral<S>::value) {
       // integer scores: the threshold used was ceil(seed)
       fb = !(c == k && double(sc[q * k + k - 1]) >= ceil(double(sd)));
@@ -421,6 +424,13 @@ __global__ void k_survivors(int64_t q0, int64_t n, int32_t k, const float* __res
   }
   if (fb_out) fb_out[q] = fb ? 1 : 0;
   if (!fb) return;
+  // a float lower bound of the k-th score, rounded down
+  float lb = 0.0f;
+  if (c == k) {
+    if constexpr (std::is_integral<S>::value) lb = __uint2float_rd(uint32_t(sc[q * k + k - 1]));
+    else lb = float(sc[q * k + k - 1]);
+  }
+  seed2[q] = lb;
   qlist[atomicAdd(qcount, 1u)] = int32_t(q);
   for (int j = 0; j < k; ++j) {
     ids[q * k + j] = -1;
@@ -445,7 +455,7 @@ struct IiibScratch {
   uint64_t* out_tmp = nullptr;
   int32_t* qlist = nullptr;
   uint32_t* qcount = nullptr;
-  int64_t qcap = 0;
+  float* seed2 = nullptr;
 };
 
 static knnj_status ensure(Index* ix, IiibScratch& sc, int64_t n_r) {
@@ -466,7 +476,8 @@ static knnj_status ensure(Index* ix, IiibScratch& sc, int64_t n_r) {
       hipMalloc(&sc.n_big, sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&sc.out_tmp, sizeof(uint64_t) * nnz1) != hipSuccess ||
       hipMalloc(&sc.qlist, sizeof(int32_t) * (n_r > 0 ? n_r : 1)) != hipSuccess ||
-      hipMalloc(&sc.qcount, sizeof(uint32_t)) != hipSuccess)
+      hipMalloc(&sc.qcount, sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&sc.seed2, sizeof(float) * (n_r > 0 ? n_r : 1)) != hipSuccess)
     return fail(KNNJ_ENOMEM, "device allocation for IIIB scratch failed");
   return KNNJ_OK;
 }
@@ -479,6 +490,7 @@ static void release(IiibScratch& sc) {
   (void)hipFree(sc.out_tmp);
   (void)hipFree(sc.qlist);
   (void)hipFree(sc.qcount);
+  (void)hipFree(sc.seed2);
 }
 
 size_t tile_smem_bytes(int tile, int k);
@@ -546,13 +558,13 @@ static knnj_status join_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t 
     if (fallback) {
       KNNJ_HIP(hipMemsetAsync(sc.qcount, 0, sizeof(uint32_t), st));
       k_survivors<S><<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-          r0, n, k, opt->theta_seed, ids, scores, cnt, sc.qlist, sc.qcount, opt->fallback_out, slots);
+          r0, n, k, opt->theta_seed, sc.seed2, ids, scores, cnt, sc.qlist, sc.qcount, opt->fallback_out, slots);
     }
     for (int32_t t = 0; t < ix->n_tiles; ++t) {
       k_iiib_tile<V><<<unsigned(n), kBlock, smem, st>>>(
           t, ix->log2_tile, ix->n_dims, k, r0, fallback ? sc.qlist : nullptr, fallback ? sc.qcount : nullptr,
           R->indptr, R->indices, (const V*)R->values, ix->offsets, ix->iiib_cut, P, ix->s_indptr, ix->iiib_fwd,
-          ix->iiib_fwd_w, fallback ? nullptr : opt->theta_seed, drop, filt, ids, scores, cnt, slots);
+          ix->iiib_fwd_w, fallback ? sc.seed2 : opt->theta_seed, drop, filt, ids, scores, cnt, slots);
     }
   }
   KNNJ_HIP(hipGetLastError());
