@@ -6,11 +6,16 @@ index and both inputs already resident in device memory.  The default
 workload is the medium one: |R| = 100,000, |S| = 1,000,000, D = 10,000,
 nnz U[50,200], Zipf(1.1) feature ids, uint8 values, k = 10.
 
-Prints one JSON line.  Extra keys beside the required ones:
-  postings_entries_per_s, postings_GBps : posting entries walked per second and
-      their algorithmic bytes (4 B per entry for uint8 data)
-  roofline : dominant kernel (the tile join) against HBM peak
-  cpu_baseline : the CPU oracle on a bounded query sample
+The headline `value` is the IIB join (Algorithm 3).  Beside it, on the same
+queries and each checked identical to the IIB output:
+  iiib.plain    Algorithm 4 as printed (split at the running threshold, every
+                candidate completed)
+  iiib.refined  the same plus the bound-filtered completion and a 4-step level
+                drop (beyond the paper; still exact)
+  iiib.learned  iiib.refined seeded by the MLP's predicted k-th score (features
+                + prediction + join timed together); miss rate = share of
+                queries whose seed was too high and that were re-run
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -36,13 +41,12 @@ def _args():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium")
-    ap.add_argument("--algo", default="iib", choices=["iib", "iiib"])
-    ap.add_argument("--bound", action="store_true", help="IIIB: bound-filtered completion")
-    ap.add_argument("--drop", type=int, default=0, help="IIIB: level drop")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--n-r", type=int, default=0, help="override |R| (quick runs only)")
     ap.add_argument("--n-s", type=int, default=0, help="override |S| (quick runs only)")
+    ap.add_argument("--n-train", type=int, default=0, help="training queries of the learned seed")
+    ap.add_argument("--no-iiib", action="store_true", help="skip the IIIB / learned-seed legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=4, help="queries checked against the oracle after timing")
@@ -74,6 +78,10 @@ def _traffic(kernel_key: str):
     return ent.get("bytes_per_launch")
 
 
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -97,12 +105,26 @@ def main():
     k = a.k or wl["k"][-1]
     n_r = a.n_r or wl["n_r"]
     n_s = a.n_s or wl["n_s"]
+    n_train = a.n_train or wl.get("n_train", 20_000)
     t0 = time.time()
-    S = synth.make(a.workload, "S", n_rows=n_s)
-    R = synth.make(a.workload, "R", n_rows=n_r)
-    t_gen = time.time() - t0
-    print("generated |S|=%d nnz=%d |R|=%d nnz=%d in %.1fs" % (S.n_rows, S.nnz, R.n_rows, R.nnz, t_gen),
-          file=sys.stderr, flush=True)
+    perm = synth.workload_perm(a.workload)
+    S = synth.make(a.workload, "S", n_rows=n_s, perm=perm)
+    R = synth.make(a.workload, "R", n_rows=n_r, perm=perm)
+    # training queries for the learned seed: the learned workload's own split, or
+    # (other workloads) the same generator as R drawn with the learned workload's
+    # training seed
+    R_train = None
+    if not a.no_iiib:
+        if "n_train" in wl:
+            R_train = synth.make(a.workload, "R_train", n_rows=n_train, perm=perm)
+        else:
+            kw = {}
+            if wl.get("r_lognormal"):
+                kw = dict(nnz_kind="lognormal", mu=wl["r_lognormal"][0], sigma=wl["r_lognormal"][1])
+            R_train = synth.draw(synth.base_seed("learned") + 4, n_train, wl["d"], wl["nnz_r"],
+                                 features=wl["features"], zipf_s=wl["zipf"] or 1.0, perm=perm, values=wl["values"],
+                                 **kw)
+    _log("generated |S|=%d nnz=%d |R|=%d nnz=%d in %.1fs" % (S.n_rows, S.nnz, R.n_rows, R.nnz, time.time() - t0))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
@@ -111,33 +133,32 @@ def main():
     ix = kj.build_index(dS, tile_width=a.tile)
     torch.cuda.synchronize()
     t_build = time.time() - tb
-    print("index built in %.3fs (T=%d, %d tiles)" % (t_build, ix.tile_width, ix.n_tiles), file=sys.stderr,
-          flush=True)
+    _log("index built in %.3fs (T=%d, %d tiles)" % (t_build, ix.tile_width, ix.n_tiles))
     stream = torch.cuda.current_stream()
     sdt = torch.int32 if S.values.dtype == np.uint8 else torch.float32
-    out = (torch.empty((n_r, k), dtype=torch.int32, device=dev), torch.empty((n_r, k), dtype=sdt, device=dev),
-           torch.empty(n_r, dtype=torch.int32, device=dev))
+
+    def outs():
+        return (torch.empty((n_r, k), dtype=torch.int32, device=dev), torch.empty((n_r, k), dtype=sdt, device=dev),
+                torch.empty(n_r, dtype=torch.int32, device=dev))
+
+    out = outs()
     stats = torch.zeros(8, dtype=torch.int64, device=dev)
-    # warmup (validated), also fills the counters
     for w in range(max(1, a.warmup)):
-        kj.knn_join(ix, dR, k, algo=a.algo, stats=stats if w == 0 else None, validate=(w == 0), out=out,
-                    bound_filter=a.bound, level_drop=a.drop)
+        kj.knn_join(ix, dR, k, stats=stats if w == 0 else None, validate=(w == 0), out=out)
         torch.cuda.synchronize()
-        print("warmup %d done" % w, file=sys.stderr, flush=True)
+        _log("warmup %d done" % w)
     walked = int(stats[kj.STAT_POSTINGS].item())
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t_wall = time.time()
     ev0.record(stream)
     for s in range(a.steps):
-        kj.knn_join(ix, dR, k, algo=a.algo, validate=False, out=out, stream=stream, bound_filter=a.bound,
-                    level_drop=a.drop)
+        kj.knn_join(ix, dR, k, validate=False, out=out, stream=stream)
+        _log("step %d launched" % s)
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.time() - t_wall
     ms = ev0.elapsed_time(ev1) / a.steps
-    print("timed %d steps: %.1f ms/step (wall %.2fs)" % (a.steps, ms, wall), file=sys.stderr, flush=True)
+    _log("timed %d steps: %.1f ms/step" % (a.steps, ms))
     qps = n_r / (ms / 1e3)
     entry_bytes = 4 if S.values.dtype == np.uint8 else 6
     eps = walked / (ms / 1e3)
@@ -147,12 +168,62 @@ def main():
     launches = ix.n_tiles
     avg_launch_ms = ms / launches
     bytes_per_launch = walked * entry_bytes / launches
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
     traffic = _traffic("k_iib_tile/%s/T%d" % (a.workload, ix.tile_width))
-    roof = {"kernel": "k_iib_tile", "bound": "hbm", "achieved": round(bytes_per_launch / (avg_launch_ms / 1e3) / 1e9, 1),
-            "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(bytes_per_launch / (avg_launch_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-            "traffic": traffic, "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": launches,
+    roof = {"kernel": "k_iib_tile", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+            "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": launches,
             "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    iiib = None
+    if not a.no_iiib:
+        iiib = {}
+
+        def timed_join(label, pre=None, **kw):
+            o = outs()
+            st = torch.zeros(8, dtype=torch.int64, device=dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            if pre is not None:
+                kw["theta_seed"] = pre()
+            kj.knn_join(ix, dR, k, algo="iiib", validate=False, out=o, stats=st, stream=stream, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            same = all(torch.equal(x, y) for x, y in zip(o, out))
+            res = {"queries_per_s": round(n_r / (t / 1e3), 1), "ms": round(t, 2), "identical_to_iib": same,
+                   "postings_walked": int(st[kj.STAT_POSTINGS]), "candidates": int(st[kj.STAT_CANDIDATES]),
+                   "completion_entries": int(st[kj.STAT_COMPLETION]), "fallbacks": int(st[kj.STAT_FALLBACKS])}
+            _log(label, json.dumps(res))
+            return res
+
+        # allocate the index-level IIIB buffers outside the timed legs
+        one = kj.DeviceCSR(dR.indptr[:2].contiguous(), dR.indices, dR.values, dR.n_dims)
+        kj.knn_join(ix, one, k, algo="iiib", validate=False)
+        iiib["plain"] = timed_join("iiib plain")
+        iiib["refined"] = timed_join("iiib refined", bound_filter=True, level_drop=4)
+        # learned seed: labels are the exact k-th scores of the training queries
+        tt = time.time()
+        dT = kj.DeviceCSR.from_host(R_train)
+        _, tsc, tcnt = kj.knn_join(ix, dT, k, validate=False)
+        y = torch.where(tcnt == k, tsc[:, k - 1].float(), torch.zeros_like(tcnt, dtype=torch.float32)).contiguous()
+        Xt = kj.Mlp.features(ix, dT)
+        mlp = kj.Mlp(seed=1)
+        losses = mlp.train(Xt, y, epochs=8, batch=512, lr=2e-3, tau=0.05, seed=2)
+        t_train = time.time() - tt
+        _log("trained the seed MLP on %d queries in %.1fs, loss %.4f -> %.4f" % (n_train, t_train, losses[0],
+                                                                                  losses[-1]))
+        res = timed_join("iiib learned", bound_filter=True, level_drop=4,
+                         pre=lambda: mlp.predict(kj.Mlp.features(ix, dR, stream=stream), stream=stream))
+        res["miss_rate"] = round(res["fallbacks"] / n_r, 4)
+        res["train_queries"] = n_train
+        res["train_s"] = round(t_train, 2)
+        res["train_loss"] = [round(losses[0], 5), round(losses[-1], 5)]
+        iiib["learned"] = res
+        iiib["learned_vs_refined_speedup"] = round(iiib["refined"]["ms"] / res["ms"], 3)
+        iiib["learned_vs_plain_speedup"] = round(iiib["plain"]["ms"] / res["ms"], 3)
 
     # spot check against the oracle (not timed)
     import oracle
@@ -167,7 +238,7 @@ def main():
                np.allclose(sc[rows], w_sc, rtol=1e-5)))
     cpu = None
     if not a.no_cpu:
-        # oracle as it stands, single thread, on a bounded sample sized from the check's speed
+        # the oracle as it stands, one thread, on a bounded sample sized from the check's speed
         per_q = t_check / max(1, len(rows))
         n_cpu = int(max(1, min(n_r, a.cpu_seconds / max(per_q, 1e-6))))
         rows_cpu = rng.choice(n_r, size=n_cpu, replace=False)
@@ -175,21 +246,20 @@ def main():
         oracle.bf_topk_rows(R, S, k, rows_cpu)
         el = time.time() - t1
         cpu = {"value": round(n_cpu / el, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
-               "sample": "%d random queries of the same workload, full S, single thread, %.1fs" % (n_cpu, el)}
+               "sample": "%d random queries of the same workload against all of S, one thread, %.1fs" % (n_cpu, el)}
     res = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8" if sdt == torch.int32 else "f32", "data": "synthetic",
-        "config": {"workload": a.workload, "algo": a.algo, "bound_filter": a.bound, "level_drop": a.drop, "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
+        "config": {"workload": a.workload, "algo": "iib", "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
                    "tile_width": ix.tile_width, "nnz_s": S.nnz, "nnz_r": R.nnz},
-        "iiib_counters": {"completion_entries": int(stats[kj.STAT_COMPLETION].item()),
-                          "candidates": int(stats[kj.STAT_CANDIDATES].item())} if a.algo == "iiib" else None,
         "postings_entries_per_s": eps, "postings_GBps": round(gbps, 1), "postings_entries_per_step": walked,
         "index_build_s": round(t_build, 3), "oracle_spot_check": {"queries": len(rows), "exact": ok},
-        "roofline": roof, "cpu_baseline": cpu,
+        "iiib": iiib, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))
-    if not ok:
+    bad = not ok or (iiib is not None and not all(iiib[v]["identical_to_iib"] for v in ("plain", "refined", "learned")))
+    if bad:
         sys.exit(1)
 
 
