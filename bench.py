@@ -48,6 +48,7 @@ def _args():
     ap.add_argument("--n-s", type=int, default=0, help="override |S| (quick runs only)")
     ap.add_argument("--n-train", type=int, default=0, help="training queries of the learned seed")
     ap.add_argument("--no-iiib", action="store_true", help="skip the IIIB / learned-seed legs")
+    ap.add_argument("--persistent", action="store_true", help="IIB: persistent per-tile launches with a work queue")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=4, help="queries checked against the oracle after timing")
@@ -153,7 +154,7 @@ def main():
     out = outs()
     stats = torch.zeros(8, dtype=torch.int64, device=dev)
     for w in range(max(1, a.warmup)):
-        kj.knn_join(ix, dR, k, stats=stats if w == 0 else None, validate=(w == 0), out=out)
+        kj.knn_join(ix, dR, k, stats=stats if w == 0 else None, validate=(w == 0), out=out, persistent=a.persistent)
         torch.cuda.synchronize()
         _log("warmup %d done" % w)
     walked = int(stats[kj.STAT_POSTINGS].item())
@@ -162,7 +163,7 @@ def main():
     torch.cuda.synchronize()
     ev0.record(stream)
     for s in range(a.steps):
-        kj.knn_join(ix, dR, k, validate=False, out=out, stream=stream)
+        kj.knn_join(ix, dR, k, validate=False, out=out, stream=stream, persistent=a.persistent)
         _log("step %d launched" % s)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -264,7 +265,8 @@ def main():
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8" if sdt == torch.int32 else "f32", "data": "synthetic",
-        "config": {"workload": a.workload, "algo": "iib", "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
+        "config": {"workload": a.workload, "algo": "iib", "schedule": "persistent" if a.persistent else "tile launches",
+                   "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
                    "tile_width": ix.tile_width, "nnz_s": S.nnz, "nnz_r": R.nnz},
         "postings_entries_per_s": eps, "postings_GBps": round(gbps, 1), "postings_entries_per_step": walked,
         "index_build_s": round(t_build, 3), "oracle_spot_check": {"queries": len(rows), "exact": ok},

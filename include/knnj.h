@@ -93,6 +93,11 @@ typedef struct {
  * completion of an s whose indexed partial score A[s] plus the bound of its
  * unindexed part cannot reach the threshold.  Results stay exact. */
 #define KNNJ_FLAG_IIIB_BOUND 2u
+/* Schedule of the IIB join.  Default: one launch per S tile with one workgroup
+ * per query, queries in longest-first order (cost = the query's postings).
+ * With this flag: one persistent launch per tile whose resident workgroups take
+ * queries, in the same order, from a device counter.  Same results. */
+#define KNNJ_FLAG_PERSISTENT 4u
 
 /* Counters accumulated into knnj_join_opts.stats (device uint64[KNNJ_STAT_COUNT]). */
 enum {
@@ -167,6 +172,10 @@ void knnj_index_free(knnj_index* ix);
  * padding (-1, 0).
  * Validation: host checks of shapes and options; unless KNNJ_FLAG_NO_VALIDATE,
  * a device check of R's structure followed by a stream synchronisation.
+ * Graph capture: with KNNJ_FLAG_NO_VALIDATE, out_count given and no more
+ * queries than an earlier call on the same index, the IIB join only enqueues
+ * kernels (no allocation, memset or synchronisation), so it can be captured
+ * into a hipGraph.
  * Errors: EINVAL, EOVERFLOW (u8 scores could exceed 2^31-1), ENOMEM, EDEVICE.
  */
 knnj_status knnj_join(const knnj_index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt,

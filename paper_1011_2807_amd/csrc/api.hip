@@ -4,6 +4,7 @@
 #include <string>
 
 #include "common.hpp"
+#include "sched.hpp"
 
 namespace knnj {
 
@@ -19,10 +20,15 @@ knnj_status build_postings(Index* ix, const int64_t* indptr, const int32_t* indi
                            hipStream_t st);
 knnj_status launch_init_out(int64_t n_rows, int32_t k, int32_t* ids, void* sc, int32_t* cnt, hipStream_t st);
 knnj_status launch_reduce_stats(const uint64_t* slots, uint64_t* out, hipStream_t st);
-knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
-                       uint64_t* slots, hipStream_t st);
+knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids, void* sc,
+                       int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids, void* sc,
                         int32_t* cnt, uint64_t* slots, hipStream_t st);
+knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k, const Sched& sch, int32_t* ids,
+                                  void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
+knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+knnj_status launch_lpt_order(int64_t n, const int64_t* r_ptr, const int32_t* r_idx, const uint32_t* list_len,
+                             uint32_t* bucket, uint32_t* hist, int32_t* order, hipStream_t st);
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st);
 size_t tile_smem_bytes(int tile);
@@ -64,6 +70,10 @@ static void free_index(Index* ix) {
   (void)hipFree(ix->rec_tmp);
   (void)hipFree(ix->dev_err);
   (void)hipFree(ix->stat_slots);
+  (void)hipFree(ix->js_order);
+  (void)hipFree(ix->js_bucket);
+  (void)hipFree(ix->js_heads);
+  (void)hipFree(ix->js_small);
   delete ix;
 }
 
@@ -218,6 +228,41 @@ static int32_t* scratch_count(int64_t n) {
   return buf;
 }
 
+// Grow the persistent-schedule scratch to n queries (the only allocation of an
+// IIB join; skipped when an earlier join was at least as large).
+static knnj_status ensure_join_scratch(Index* ix, int64_t n) {
+  if (ix->js_small == nullptr && (hipMalloc(&ix->js_small, sizeof(uint32_t) * 64) != hipSuccess ||
+                                  hipMalloc(&ix->js_heads, sizeof(uint32_t) * 2 * size_t(ix->n_tiles)) != hipSuccess))
+    return fail(KNNJ_ENOMEM, "join scratch allocation failed");
+  if (n <= ix->js_cap) return KNNJ_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ix->js_order);
+  (void)hipFree(ix->js_bucket);
+  ix->js_order = nullptr;
+  ix->js_bucket = nullptr;
+  ix->js_cap = 0;
+  if (hipMalloc(&ix->js_order, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&ix->js_bucket, sizeof(uint32_t) * n) != hipSuccess)
+    return fail(KNNJ_ENOMEM, "join scratch allocation failed");
+  ix->js_cap = n;
+  return KNNJ_OK;
+}
+
+// Schedule over `n` positions of `order` (or a device count when count != nullptr),
+// using per-tile counter bank `bank` (0 or 1).
+Sched make_sched(Index* ix, int64_t n, const int32_t* order, const uint32_t* count, int bank) {
+  Sched s;
+  s.head = ix->js_heads + size_t(bank) * ix->n_tiles;
+  s.order = order;
+  s.count = count;
+  s.n = n;
+  return s;
+}
+
+knnj_status reset_sched(Index* ix, int bank, hipStream_t st) {
+  return launch_fill_u32(ix->js_heads + size_t(bank) * ix->n_tiles, ix->n_tiles, 0u, st);
+}
+
 knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids,
                       void* sc, int32_t* cnt, void* stream) {
   g_last_error.clear();
@@ -242,12 +287,27 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
   uint64_t* slots = nullptr;
   if (o.stats) {
     slots = ix->stat_slots;
-    KNNJ_HIP(hipMemsetAsync(slots, 0, sizeof(uint64_t) * 256 * KNNJ_STAT_COUNT, st));
+    if ((rc = launch_fill_u32(reinterpret_cast<uint32_t*>(slots), 2 * 256 * KNNJ_STAT_COUNT, 0u, st)) != KNNJ_OK)
+      return rc;
   }
-  if (o.algo == KNNJ_IIB) rc = launch_iib(ix, R, k, ids, sc, cnt, slots, st);
-  else rc = launch_iiib(ix, R, k, &o, ids, sc, cnt, slots, st);
+  // longest-first query order (cost = the query's IIB postings), used by every schedule
+  if ((rc = ensure_join_scratch(ix, R->n_rows)) != KNNJ_OK) return rc;
+  if ((rc = launch_lpt_order(R->n_rows, R->indptr, R->indices, ix->list_len, ix->js_bucket, ix->js_small,
+                             ix->js_order, st)) != KNNJ_OK)
+    return rc;
+  if (o.algo == KNNJ_IIB) {
+    if (o.flags & KNNJ_FLAG_PERSISTENT) {
+      if ((rc = reset_sched(ix, 0, st)) != KNNJ_OK) return rc;
+      rc = launch_iib_persistent(ix, R, k, make_sched(ix, R->n_rows, ix->js_order, nullptr, 0), ids, sc, cnt, slots,
+                                 st);
+    } else {
+      rc = launch_iib(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
+    }
+  } else {
+    rc = launch_iiib(ix, R, k, &o, ids, sc, cnt, slots, st);
+  }
   if (rc != KNNJ_OK) return rc;
-  if (o.stats) return launch_reduce_stats(slots, o.stats, st);
+  if (o.stats && (rc = launch_reduce_stats(slots, o.stats, st)) != KNNJ_OK) return rc;
   return KNNJ_OK;
 }
 

@@ -58,6 +58,13 @@ struct Index {
   float* iiib_fwd_w = nullptr;       // f32 weights of iiib_fwd
   uint32_t* iiib_cut = nullptr;      // [(tile, d), level]: entries of list (tile, d) with level >= that level
   uint64_t* rec_tmp = nullptr;       // build scratch (8 bytes per entry)
+  // join scratch of the persistent schedule (grow-only: allocated when a join has
+  // more queries than any earlier one)
+  int64_t js_cap = 0;
+  int32_t* js_order = nullptr;       // query order (longest first)
+  uint32_t* js_bucket = nullptr;     // cost bucket per query
+  uint32_t* js_heads = nullptr;      // per-tile queue counters [n_tiles]
+  uint32_t* js_small = nullptr;      // [0, 64) cost histogram
   // small persistent scratch
   int32_t* dev_err = nullptr;        // validation result
   uint64_t* stat_slots = nullptr;    // spread counters, reduced into caller stats

@@ -7,6 +7,7 @@
 // are exact for integer scores.  The lists (t, d) of all features of r are
 // walked as one concatenated sequence of 16-byte groups shared out over teams of
 // lanes (see walk_lists), so lanes stay busy even when most lists are short.
+#include "sched.hpp"
 #include "walk.hpp"
 
 namespace knnj {
@@ -37,10 +38,43 @@ __global__ void k_reduce_stats(const uint64_t* slots, int n_slots, uint64_t* out
   if (threadIdx.x == 0 && part[0] != 0) atomicAdd((unsigned long long*)&out[blockIdx.x], (unsigned long long)part[0]);
 }
 
-// IIB on tile `tile` for queries q0 + blockIdx.x.
+// IIB for query q on tile `tile` (one workgroup).  acc: T scores in local
+// memory; stage: the list table / selection workspace; tmp: scan scratch.
+template <typename V>
+__device__ __forceinline__ uint64_t iib_item(int32_t tile, int64_t q, int32_t log2_tile, int32_t n_dims, int32_t k,
+                                             const int64_t* __restrict__ r_ptr, const int32_t* __restrict__ r_idx,
+                                             const V* __restrict__ r_val, const int64_t* __restrict__ offsets,
+                                             Postings<V> P, int32_t* __restrict__ out_ids,
+                                             typename ScoreOf<V>::T* __restrict__ out_sc, int32_t* __restrict__ out_cnt,
+                                             bool count, typename ScoreOf<V>::T* acc, char* stage, uint32_t* tmp) {
+  using S = typename ScoreOf<V>::T;
+  const int T = 1 << log2_tile;
+  const int64_t s_base = int64_t(tile) << log2_tile;
+  // rows past the end of S have no postings, so their slots stay 0
+  for (int i = threadIdx.x; i < T / 4; i += kBlock) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
+  const int64_t rb = r_ptr[q], re = r_ptr[q + 1];
+  const int64_t key0 = int64_t(tile) * n_dims;
+  uint64_t walked = 0;
+  for (int64_t cb = rb; cb < re; cb += kSegChunk) {
+    const int n = int(re - cb < kSegChunk ? re - cb : kSegChunk);
+    const uint32_t total = stage_lists<V, S>(stage, tmp, key0, r_idx, r_val, cb, n, offsets);
+    walk_lists<V, S>(acc, stage, n, total, P);
+    if (count) {
+      // exact entries walked: sum of list lengths of this pass
+      uint32_t l = threadIdx.x < n ? reinterpret_cast<const uint32_t*>(stage + kMetaOff)[threadIdx.x] >> 2 : 0u;
+      walked += block_sum(l, tmp);
+    }
+    __syncthreads();
+  }
+  tile_select<S, true>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q, select_smem(stage, k, tmp));
+  return walked;
+}
+
+// One launch per tile: workgroup b joins query order[q0 + b] (or q0 + b).
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_tile, int64_t n_s, int32_t n_dims,
-                                                     int32_t k, int64_t q0, const int64_t* __restrict__ r_ptr,
+                                                     int32_t k, int64_t q0, const int32_t* __restrict__ order,
+                                                     const int64_t* __restrict__ r_ptr,
                                                      const int32_t* __restrict__ r_idx, const V* __restrict__ r_val,
                                                      const int64_t* __restrict__ offsets, Postings<V> P,
                                                      int32_t* __restrict__ out_ids,
@@ -49,30 +83,39 @@ __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_
   using S = typename ScoreOf<V>::T;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint32_t tmp[kBlock / kWave + 1];
-  const int T = 1 << log2_tile;
+  (void)n_s;
   S* acc = reinterpret_cast<S*>(smem);
-  char* stage = smem + size_t(T) * 4;
+  char* stage = smem + (size_t(4) << log2_tile);
+  const int64_t q = order ? int64_t(order[q0 + blockIdx.x]) : q0 + blockIdx.x;
+  const uint64_t walked = iib_item<V>(tile, q, log2_tile, n_dims, k, r_ptr, r_idx, r_val, offsets, P,
+                                      out_ids, out_sc, out_cnt, slots != nullptr, acc, stage, tmp);
+  if (threadIdx.x == 0 && slots) atomicAdd((unsigned long long*)&slots[KNNJ_STAT_POSTINGS * 256 + (blockIdx.x & 255)],
+                                           (unsigned long long)walked);
+}
 
-  const int64_t q = q0 + blockIdx.x;
-  const int64_t s_base = int64_t(tile) << log2_tile;
-  (void)n_s;  // rows past the end of S have no postings, so their slots stay 0
-  for (int i = threadIdx.x; i < T / 4; i += kBlock) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
-
-  const int64_t rb = r_ptr[q], re = r_ptr[q + 1];
-  const int64_t key0 = int64_t(tile) * n_dims;
+// Persistent launch for tile `tile` (see sched.hpp).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_iib_persistent(Sched sch, int32_t tile, int32_t log2_tile, int32_t n_dims,
+                                                           int32_t k, const int64_t* __restrict__ r_ptr,
+                                                           const int32_t* __restrict__ r_idx,
+                                                           const V* __restrict__ r_val,
+                                                           const int64_t* __restrict__ offsets, Postings<V> P,
+                                                           int32_t* __restrict__ out_ids,
+                                                           typename ScoreOf<V>::T* __restrict__ out_sc,
+                                                           int32_t* __restrict__ out_cnt, uint64_t* __restrict__ slots) {
+  using S = typename ScoreOf<V>::T;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ uint32_t tmp[kBlock / kWave + 1];
+  __shared__ uint32_t slot[1];
+  S* acc = reinterpret_cast<S*>(smem);
+  char* stage = smem + (size_t(4) << log2_tile);
   uint64_t walked = 0;
-  for (int64_t cb = rb; cb < re; cb += kSegChunk) {
-    const int n = int(re - cb < kSegChunk ? re - cb : kSegChunk);
-    const uint32_t total = stage_lists<V, S>(stage, tmp, key0, r_idx, r_val, cb, n, offsets);
-    walk_lists<V, S>(acc, stage, n, total, P);
-    if (slots) {
-      // exact entries walked: sum of list lengths of this pass
-      uint32_t l = threadIdx.x < n ? reinterpret_cast<const uint32_t*>(stage + kMetaOff)[threadIdx.x] >> 2 : 0u;
-      walked += block_sum(l, tmp);
-    }
-    __syncthreads();
+  int64_t first, n;
+  while (sched_chunk(sch, tile, &first, &n, slot)) {
+    for (int64_t p = first; p < first + kChunk && p < n; ++p)
+      walked += iib_item<V>(tile, sched_query(sch, p), log2_tile, n_dims, k, r_ptr, r_idx, r_val, offsets, P, out_ids,
+                            out_sc, out_cnt, slots != nullptr, acc, stage, tmp);
   }
-  tile_select<S, true>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q, select_smem(stage, k, tmp));
   if (threadIdx.x == 0 && slots) atomicAdd((unsigned long long*)&slots[KNNJ_STAT_POSTINGS * 256 + (blockIdx.x & 255)],
                                            (unsigned long long)walked);
 }
@@ -148,24 +191,56 @@ knnj_status launch_reduce_stats(const uint64_t* slots, uint64_t* out, hipStream_
 
 static const int64_t kMaxGrid = 1ll << 30;
 
-knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
-                       uint64_t* slots, hipStream_t st) {
+knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids, void* sc,
+                       int32_t* cnt, uint64_t* slots, hipStream_t st) {
   const size_t smem = tile_smem_bytes(ix->tile, k);
   for (int32_t t = 0; t < ix->n_tiles; ++t) {
     for (int64_t q0 = 0; q0 < R->n_rows; q0 += kMaxGrid) {
       const unsigned g = unsigned(R->n_rows - q0 < kMaxGrid ? R->n_rows - q0 : kMaxGrid);
       if (ix->dtype == KNNJ_U8) {
         Postings<uint8_t> P{reinterpret_cast<const uint4*>(ix->post_u8)};
-        k_iib_tile<uint8_t><<<g, kBlock, smem, st>>>(t, ix->log2_tile, ix->n_rows, ix->n_dims, k, q0, R->indptr,
+        k_iib_tile<uint8_t><<<g, kBlock, smem, st>>>(t, ix->log2_tile, ix->n_rows, ix->n_dims, k, q0, order, R->indptr,
                                                      R->indices, (const uint8_t*)R->values, ix->offsets, P, ids,
                                                      (uint32_t*)sc, cnt, slots);
       } else {
         Postings<float> P{reinterpret_cast<const uint2*>(ix->post_s), reinterpret_cast<const float4*>(ix->post_w)};
-        k_iib_tile<float><<<g, kBlock, smem, st>>>(t, ix->log2_tile, ix->n_rows, ix->n_dims, k, q0, R->indptr,
+        k_iib_tile<float><<<g, kBlock, smem, st>>>(t, ix->log2_tile, ix->n_rows, ix->n_dims, k, q0, order, R->indptr,
                                                    R->indices, (const float*)R->values, ix->offsets, P, ids,
                                                    (float*)sc, cnt, slots);
       }
     }
+  }
+  KNNJ_HIP(hipGetLastError());
+  return KNNJ_OK;
+}
+
+// Workgroups of the persistent launch: every CU filled to its occupancy.
+template <typename K>
+static unsigned persistent_grid(K kernel, size_t smem, int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, smem) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  return unsigned(per_cu * cus);
+}
+
+knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k, const Sched& sch, int32_t* ids,
+                                  void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st) {
+  const size_t smem = tile_smem_bytes(ix->tile, k);
+  if (ix->dtype == KNNJ_U8) {
+    Postings<uint8_t> P{reinterpret_cast<const uint4*>(ix->post_u8)};
+    const unsigned g = persistent_grid(k_iib_persistent<uint8_t>, smem, ix->device);
+    for (int32_t t = 0; t < ix->n_tiles; ++t)
+      k_iib_persistent<uint8_t><<<g, kBlock, smem, st>>>(sch, t, ix->log2_tile, ix->n_dims, k, R->indptr, R->indices,
+                                                         (const uint8_t*)R->values, ix->offsets, P, ids,
+                                                         (uint32_t*)sc, cnt, slots);
+  } else {
+    Postings<float> P{reinterpret_cast<const uint2*>(ix->post_s), reinterpret_cast<const float4*>(ix->post_w)};
+    const unsigned g = persistent_grid(k_iib_persistent<float>, smem, ix->device);
+    for (int32_t t = 0; t < ix->n_tiles; ++t)
+      k_iib_persistent<float><<<g, kBlock, smem, st>>>(sch, t, ix->log2_tile, ix->n_dims, k, R->indptr, R->indices,
+                                                       (const float*)R->values, ix->offsets, P, ids, (float*)sc, cnt,
+                                                       slots);
   }
   KNNJ_HIP(hipGetLastError());
   return KNNJ_OK;

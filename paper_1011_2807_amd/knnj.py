@@ -22,6 +22,7 @@ KNNJ_U8, KNNJ_F32 = 0, 1
 KNNJ_IIB, KNNJ_IIIB = 0, 1
 KNNJ_FLAG_NO_VALIDATE = 1
 KNNJ_FLAG_IIIB_BOUND = 2
+KNNJ_FLAG_PERSISTENT = 4
 STAT_POSTINGS, STAT_COMPLETION, STAT_CANDIDATES, STAT_FALLBACKS, STAT_COUNT = 0, 1, 2, 3, 8
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "EUNSUPPORTED"}
 
@@ -194,7 +195,7 @@ def _outputs(n: int, k: int, dtype: int, out):
 def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows: int = 0,
              theta_seed: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
              fallback_out: Optional[torch.Tensor] = None, validate: bool = True, bound_filter: bool = False,
-             level_drop: int = 0, out=None, stream=None):
+             level_drop: int = 0, persistent: bool = False, out=None, stream=None):
     """Exact top-k of every row of R against the indexed S.
 
     Returns (ids int32[n,k], scores int32|float32[n,k], count int32[n]) on the device.
@@ -202,12 +203,14 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     k-th score guesses (IIIB).  stats: optional int64[8] device tensor of
     counters (added to).  fallback_out: optional uint8[n] device tensor.
     bound_filter / level_drop: IIIB refinements (see knnj.h); results stay exact.
+    persistent: one persistent launch per S tile with a device work queue (IIB).
     """
     lib = load_library()
     ids, sc, cnt = _outputs(R.n_rows, k, index.dtype, out)
     o = _JoinOpts()
     o.algo = KNNJ_IIIB if algo == "iiib" else KNNJ_IIB
-    o.flags = (0 if validate else KNNJ_FLAG_NO_VALIDATE) | (KNNJ_FLAG_IIIB_BOUND if bound_filter else 0)
+    o.flags = ((0 if validate else KNNJ_FLAG_NO_VALIDATE) | (KNNJ_FLAG_IIIB_BOUND if bound_filter else 0) |
+               (KNNJ_FLAG_PERSISTENT if persistent else 0))
     o.level_drop = int(level_drop)
     o.r_block_rows = int(r_block_rows)
     if theta_seed is not None:

@@ -1,0 +1,58 @@
+"""The IIB join captured into a HIP graph: k = 1 and k = 10 in one graph,
+replayed several times with eager work between replays, every replay checked
+against the eager result."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_exact
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_1011_2807_amd as kj  # noqa: E402
+
+
+def test_graph_k1_and_k10_replays():
+    S = synth.make("batched", "S", n_rows=30_000)
+    R = synth.make("batched", "R", n_rows=500)
+    dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+    ix = kj.build_index(dS, tile_width=4096)
+    n = R.n_rows
+    outs = {}
+    for k in (1, 10):
+        outs[k] = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+                   torch.empty((n, k), dtype=torch.int32, device="cuda"),
+                   torch.empty(n, dtype=torch.int32, device="cuda"))
+    # eager reference (also grows the library's join scratch outside the capture)
+    eager = {k: [x.clone() for x in kj.knn_join(ix, dR, k)] for k in (1, 10)}
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for k in (1, 10):
+            kj.knn_join(ix, dR, k, validate=False, out=outs[k])
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in (1, 10):
+            for x in outs[k]:
+                x.fill_(-7)
+        # eager work between replays
+        kj.knn_join(ix, dR, 3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in (1, 10):
+            for a, b in zip(outs[k], eager[k]):
+                assert torch.equal(a, b), (rep, k)
+    # k = 1 is the first column of k = 10
+    assert torch.equal(outs[1][0][:, 0], outs[10][0][:, 0])
+    assert torch.equal(outs[1][1][:, 0], outs[10][1][:, 0])
+    rows = list(range(0, n, 50))
+    want = oracle.bf_topk_rows(R, S, 10, rows)
+    assert_exact(tuple(x[rows] for x in outs[10]), want, "graph replay k=10")

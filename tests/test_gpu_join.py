@@ -77,17 +77,32 @@ def test_list_lengths(tiny):
     np.testing.assert_array_equal(ll, np.bincount(S.indices, minlength=S.n_dims))
 
 
-@pytest.mark.parametrize("tile,k", [(1024, 10), (4096, 1), (8192, 37)])
-def test_zipf_multi_tile_ragged(tile, k):
-    """Medium-workload recipe at 20,500 S rows (several tiles plus a ragged one)."""
+@pytest.mark.parametrize("tile,k,per_tile", [(1024, 10, False), (4096, 1, True), (8192, 37, False), (2048, 10, True)])
+def test_zipf_multi_tile_ragged(tile, k, per_tile):
+    """Medium-workload recipe at 20,500 S rows (several tiles plus a ragged one),
+    persistent schedule and one launch per tile."""
     S = synth.make("medium", "S", n_rows=20_500)
     R = synth.make("medium", "R", n_rows=120)
-    print("zipf tile", tile, "k", k, flush=True)
+    print("zipf tile", tile, "k", k, "persistent", per_tile, flush=True)
     want = oracle.bf_topk(R, S, k)
     ix = kj.build_index(_dev(S), tile_width=tile)
-    got = kj.knn_join(ix, _dev(R), k)
+    got = kj.knn_join(ix, _dev(R), k, persistent=per_tile)
     torch.cuda.synchronize()
     assert_exact(got, want, "zipf IIB T=%d k=%d" % (tile, k))
+
+
+def test_uneven_queries_persistent_schedule():
+    """Lognormal query lengths (batched-workload recipe): persistent schedule with
+    the longest-first order equals persistent and the oracle."""
+    S = synth.make("batched", "S", n_rows=12_000)
+    R = synth.make("batched", "R", n_rows=300)
+    ix = kj.build_index(_dev(S), tile_width=2048)
+    want = oracle.bf_topk(R, S, 10)
+    a = kj.knn_join(ix, _dev(R), 10)
+    b = kj.knn_join(ix, _dev(R), 10, persistent=True)
+    torch.cuda.synchronize()
+    assert_exact(a, want, "batched per-tile launches")
+    assert_exact(b, want, "batched persistent")
 
 
 def test_edge_cases_empty_rows_padding_ties():
@@ -100,9 +115,10 @@ def test_edge_cases_empty_rows_padding_ties():
         want = oracle.bf_topk(R, S, k)
         for tile in (256, 512):
             ix = kj.build_index(_dev(S), tile_width=tile)
-            got = kj.knn_join(ix, _dev(R), k)
-            torch.cuda.synchronize()
-            assert_exact(got, want, "edge IIB k=%d T=%d" % (k, tile))
+            for per_tile in (False, True):
+                got = kj.knn_join(ix, _dev(R), k, persistent=per_tile)
+                torch.cuda.synchronize()
+                assert_exact(got, want, "edge IIB k=%d T=%d per-tile=%s" % (k, tile, per_tile))
         got = kj.knn_join_bf(_dev(S), _dev(R), k)
         torch.cuda.synchronize()
         assert_exact(got, want, "edge BF k=%d" % k)
