@@ -173,9 +173,9 @@ void knnj_index_free(knnj_index* ix);
  * Validation: host checks of shapes and options; unless KNNJ_FLAG_NO_VALIDATE,
  * a device check of R's structure followed by a stream synchronisation.
  * Graph capture: with KNNJ_FLAG_NO_VALIDATE, out_count given and no more
- * queries than an earlier call on the same index, the IIB join only enqueues
- * kernels (no allocation, memset or synchronisation), so it can be captured
- * into a hipGraph.
+ * queries than an earlier call of the same algorithm on the same index, a join
+ * only enqueues kernels (no allocation, memset or synchronisation), so it can
+ * be captured into a hipGraph.
  * Errors: EINVAL, EOVERFLOW (u8 scores could exceed 2^31-1), ENOMEM, EDEVICE.
  */
 knnj_status knnj_join(const knnj_index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt,

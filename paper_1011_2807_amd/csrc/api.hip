@@ -22,8 +22,8 @@ knnj_status launch_init_out(int64_t n_rows, int32_t k, int32_t* ids, void* sc, i
 knnj_status launch_reduce_stats(const uint64_t* slots, uint64_t* out, hipStream_t st);
 knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids, void* sc,
                        int32_t* cnt, uint64_t* slots, hipStream_t st);
-knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids, void* sc,
-                        int32_t* cnt, uint64_t* slots, hipStream_t st);
+knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, const int32_t* order,
+                        int32_t* ids, void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k, const Sched& sch, int32_t* ids,
                                   void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
@@ -67,6 +67,13 @@ static void free_index(Index* ix) {
   (void)hipFree(ix->iiib_fwd);
   (void)hipFree(ix->iiib_fwd_w);
   (void)hipFree(ix->iiib_cut);
+  (void)hipFree(ix->iiib_freq);
+  (void)hipFree(ix->iiib_maxw);
+  (void)hipFree(ix->iiib_big);
+  (void)hipFree(ix->iiib_small);
+  (void)hipFree(ix->iiib_out_tmp);
+  (void)hipFree(ix->iiib_qlist);
+  (void)hipFree(ix->iiib_seed2);
   (void)hipFree(ix->rec_tmp);
   (void)hipFree(ix->dev_err);
   (void)hipFree(ix->stat_slots);
@@ -304,7 +311,7 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
       rc = launch_iib(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
     }
   } else {
-    rc = launch_iiib(ix, R, k, &o, ids, sc, cnt, slots, st);
+    rc = launch_iiib(ix, R, k, &o, ix->js_order, ids, sc, cnt, slots, st);
   }
   if (rc != KNNJ_OK) return rc;
   if (o.stats && (rc = launch_reduce_stats(slots, o.stats, st)) != KNNJ_OK) return rc;

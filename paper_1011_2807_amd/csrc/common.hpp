@@ -57,6 +57,14 @@ struct Index {
   uint32_t* iiib_fwd = nullptr;      // each S row in the block's dimension order (see iiib.hip)
   float* iiib_fwd_w = nullptr;       // f32 weights of iiib_fwd
   uint32_t* iiib_cut = nullptr;      // [(tile, d), level]: entries of list (tile, d) with level >= that level
+  uint32_t* iiib_freq = nullptr;     // freq_d(B_r)
+  uint32_t* iiib_maxw = nullptr;     // maxWeight_d(B_r) (value bits)
+  int64_t* iiib_big = nullptr;       // lists queued for the long-list sorts
+  uint32_t* iiib_small = nullptr;    // [0] queued long lists, [1] fallback queue length
+  uint64_t* iiib_out_tmp = nullptr;  // sort scratch (8 bytes per entry)
+  int32_t* iiib_qlist = nullptr;     // fallback queue
+  float* iiib_seed2 = nullptr;       // fallback seeds (proven lower bounds)
+  int64_t iiib_qcap = 0;
   uint64_t* rec_tmp = nullptr;       // build scratch (8 bytes per entry)
   // join scratch of the persistent schedule (grow-only: allocated when a join has
   // more queries than any earlier one)

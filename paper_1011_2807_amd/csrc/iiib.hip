@@ -229,14 +229,16 @@ __global__ __launch_bounds__(kWave) void k_split_scatter(int64_t n_s, int32_t n_
 // local array and reads the slots back in order (payloads are never 0 bits).
 constexpr int kBucketSlots = 8192;
 __global__ void k_sort_buckets(const int64_t* __restrict__ offsets, const int64_t* __restrict__ big,
-                               const uint32_t* __restrict__ cut, uint64_t* __restrict__ rec,
-                               uint64_t* __restrict__ out_tmp, int32_t tile) {
+                               const uint32_t* __restrict__ n_big, const uint32_t* __restrict__ cut,
+                               uint64_t* __restrict__ rec, uint64_t* __restrict__ out_tmp, int32_t tile) {
   extern __shared__ uint32_t slots[];  // kBucketSlots
   __shared__ uint32_t tmp[kBlock / kWave + 1];
   __shared__ uint32_t written;
-  const int64_t key = big[blockIdx.x];
+  const uint32_t nb = *n_big;
+  for (uint32_t item = blockIdx.x; item < nb; item += gridDim.x) {
+  const int64_t key = big[item];
   const int64_t b = offsets[key], e = offsets[key + 1];
-  if (e - b <= 2048) return;
+  if (e - b <= 2048) continue;
   const uint32_t* c = cut + key * kLevels;
   uint32_t beg = 0;
   for (int l = kLevels - 1; l >= 0; --l) {
@@ -273,6 +275,7 @@ __global__ void k_sort_buckets(const int64_t* __restrict__ offsets, const int64_
     }
     beg = end;
   }
+  }
 }
 
 __global__ void k_finalize_iiib_u8(const uint64_t* __restrict__ rec, int64_t n, uint32_t* __restrict__ post) {
@@ -294,8 +297,8 @@ __global__ void k_finalize_iiib_f32(const uint64_t* __restrict__ rec, int64_t n,
 // dimensions | stage.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_iiib_tile(
-    int32_t tile, int32_t log2_tile, int32_t n_dims, int32_t k, int64_t q0, const int32_t* __restrict__ qlist,
-    const uint32_t* __restrict__ qcount, const int64_t* __restrict__ r_ptr, const int32_t* __restrict__ r_idx,
+    int32_t tile, int32_t log2_tile, int32_t n_dims, int32_t k, int64_t q0, const int32_t* __restrict__ order,
+    const int32_t* __restrict__ qlist, const uint32_t* __restrict__ qcount, const int64_t* __restrict__ r_ptr, const int32_t* __restrict__ r_idx,
     const V* __restrict__ r_val, const int64_t* __restrict__ offsets, const uint32_t* __restrict__ cut,
     Postings<V> P, const int64_t* __restrict__ s_ptr, const uint32_t* __restrict__ fwd,
     const float* __restrict__ fwd_w, const float* __restrict__ seed, int32_t level_drop, int32_t bound_filter,
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
     if (blockIdx.x >= *qcount) return;
     q = qlist[blockIdx.x];
   } else {
-    q = q0 + blockIdx.x;
+    q = order ? int64_t(order[q0 + blockIdx.x]) : q0 + blockIdx.x;
   }
   const int T = 1 << log2_tile;
   S* acc = reinterpret_cast<S*>(smem);
@@ -441,24 +444,18 @@ __global__ void k_survivors(int64_t q0, int64_t n, int32_t k, const float* __res
 }
 
 // ---------------------------------------------------------------- host driver
-knnj_status exclusive_scan_u32(const uint32_t* in, int64_t n, int64_t* out, int64_t* partial, hipStream_t st);
+knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 __global__ void k_sort_small(const int64_t* __restrict__ offsets, int64_t n_keys, uint64_t* __restrict__ rec,
                              int64_t* __restrict__ big, uint32_t* __restrict__ n_big);
 __global__ void k_sort_mid(const int64_t* __restrict__ offsets, const int64_t* __restrict__ big,
-                           uint64_t* __restrict__ rec);
+                           const uint32_t* __restrict__ n_big, uint64_t* __restrict__ rec);
+size_t tile_smem_bytes(int tile, int k);
 
-struct IiibScratch {
-  uint32_t* freq = nullptr;
-  uint32_t* maxw = nullptr;
-  int64_t* big = nullptr;
-  uint32_t* n_big = nullptr;
-  uint64_t* out_tmp = nullptr;
-  int32_t* qlist = nullptr;
-  uint32_t* qcount = nullptr;
-  float* seed2 = nullptr;
-};
+constexpr unsigned kSortGrid = 4096;  // workgroups striding over the queued long lists
 
-static knnj_status ensure(Index* ix, IiibScratch& sc, int64_t n_r) {
+// Index-level IIIB buffers (first use) and per-query ones (grow-only).  The only
+// allocations of an IIIB join; a later join with no more queries allocates nothing.
+static knnj_status ensure_iiib(Index* ix, int64_t n_r) {
   const int64_t n_keys = int64_t(ix->n_tiles) * ix->n_dims;
   const size_t nnz1 = size_t(ix->nnz > 0 ? ix->nnz : 1);
   if (!ix->iiib_fwd) {
@@ -467,69 +464,62 @@ static knnj_status ensure(Index* ix, IiibScratch& sc, int64_t n_r) {
         (ix->dtype == KNNJ_F32 && hipMalloc(&ix->iiib_fwd_w, sizeof(float) * nnz1) != hipSuccess) ||
         (ix->dtype == KNNJ_U8 && hipMalloc(&ix->iiib_post, sizeof(uint32_t) * (nnz1 + kPostPad)) != hipSuccess) ||
         (ix->dtype == KNNJ_F32 && (hipMalloc(&ix->iiib_post_s, sizeof(uint16_t) * (nnz1 + kPostPad)) != hipSuccess ||
-                                   hipMalloc(&ix->iiib_post_w, sizeof(float) * (nnz1 + kPostPad)) != hipSuccess)))
+                                   hipMalloc(&ix->iiib_post_w, sizeof(float) * (nnz1 + kPostPad)) != hipSuccess)) ||
+        hipMalloc(&ix->iiib_freq, sizeof(uint32_t) * ix->n_dims) != hipSuccess ||
+        hipMalloc(&ix->iiib_maxw, sizeof(uint32_t) * ix->n_dims) != hipSuccess ||
+        hipMalloc(&ix->iiib_big, sizeof(int64_t) * (n_keys > 0 ? n_keys : 1)) != hipSuccess ||
+        hipMalloc(&ix->iiib_small, sizeof(uint32_t) * 8) != hipSuccess ||
+        hipMalloc(&ix->iiib_out_tmp, sizeof(uint64_t) * nnz1) != hipSuccess)
       return fail(KNNJ_ENOMEM, "device allocation for the IIIB index failed");
   }
-  if (hipMalloc(&sc.freq, sizeof(uint32_t) * ix->n_dims) != hipSuccess ||
-      hipMalloc(&sc.maxw, sizeof(uint32_t) * ix->n_dims) != hipSuccess ||
-      hipMalloc(&sc.big, sizeof(int64_t) * (n_keys > 0 ? n_keys : 1)) != hipSuccess ||
-      hipMalloc(&sc.n_big, sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&sc.out_tmp, sizeof(uint64_t) * nnz1) != hipSuccess ||
-      hipMalloc(&sc.qlist, sizeof(int32_t) * (n_r > 0 ? n_r : 1)) != hipSuccess ||
-      hipMalloc(&sc.qcount, sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&sc.seed2, sizeof(float) * (n_r > 0 ? n_r : 1)) != hipSuccess)
-    return fail(KNNJ_ENOMEM, "device allocation for IIIB scratch failed");
+  if (n_r > ix->iiib_qcap) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ix->iiib_qlist);
+    (void)hipFree(ix->iiib_seed2);
+    ix->iiib_qlist = nullptr;
+    ix->iiib_seed2 = nullptr;
+    ix->iiib_qcap = 0;
+    if (hipMalloc(&ix->iiib_qlist, sizeof(int32_t) * n_r) != hipSuccess ||
+        hipMalloc(&ix->iiib_seed2, sizeof(float) * n_r) != hipSuccess)
+      return fail(KNNJ_ENOMEM, "device allocation for the IIIB fallback queue failed");
+    ix->iiib_qcap = n_r;
+  }
   return KNNJ_OK;
 }
-
-static void release(IiibScratch& sc) {
-  (void)hipFree(sc.freq);
-  (void)hipFree(sc.maxw);
-  (void)hipFree(sc.big);
-  (void)hipFree(sc.n_big);
-  (void)hipFree(sc.out_tmp);
-  (void)hipFree(sc.qlist);
-  (void)hipFree(sc.qcount);
-  (void)hipFree(sc.seed2);
-}
-
-size_t tile_smem_bytes(int tile, int k);
 
 static size_t iiib_smem(const Index* ix, int k) {
   const size_t rbytes = (size_t(ix->n_dims) * (ix->dtype == KNNJ_U8 ? 1 : 4) + 15) & ~size_t(15);
   return tile_smem_bytes(ix->tile, k) + rbytes;
 }
 
-// Builds the IIIB index of R rows [r0, r1) into ix->iiib_*.
+// Builds the IIIB index of R rows [r0, r1) into ix->iiib_*.  Enqueues kernels only.
 template <typename V>
-static knnj_status build_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t r1, IiibScratch& sc,
-                               hipStream_t st) {
+static knnj_status build_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t r1, hipStream_t st) {
   const int64_t n_keys = int64_t(ix->n_tiles) * ix->n_dims;
-  KNNJ_HIP(hipMemsetAsync(sc.freq, 0, sizeof(uint32_t) * ix->n_dims, st));
-  KNNJ_HIP(hipMemsetAsync(sc.maxw, 0, sizeof(uint32_t) * ix->n_dims, st));
-  KNNJ_HIP(hipMemsetAsync(ix->iiib_cut, 0, sizeof(uint32_t) * size_t(n_keys) * kLevels, st));
-  KNNJ_HIP(hipMemsetAsync(sc.n_big, 0, sizeof(uint32_t), st));
-  k_block_stats<V><<<2048, kBlock, 0, st>>>(r0, r1, R->indptr, R->indices, (const V*)R->values, sc.freq, sc.maxw);
+  uint32_t* n_big = ix->iiib_small;
+  knnj_status rc;
+  if ((rc = launch_fill_u32(ix->iiib_freq, ix->n_dims, 0u, st)) != KNNJ_OK ||
+      (rc = launch_fill_u32(ix->iiib_maxw, ix->n_dims, 0u, st)) != KNNJ_OK ||
+      (rc = launch_fill_u32(ix->iiib_cut, n_keys * kLevels, 0u, st)) != KNNJ_OK ||
+      (rc = launch_fill_u32(n_big, 1, 0u, st)) != KNNJ_OK)
+    return rc;
+  k_block_stats<V><<<2048, kBlock, 0, st>>>(r0, r1, R->indptr, R->indices, (const V*)R->values, ix->iiib_freq,
+                                            ix->iiib_maxw);
   if (ix->n_rows > 0) {
     int p = 1;
     while (p < ix->max_row_nnz) p <<= 1;
     k_split_rows<V><<<unsigned(ix->n_rows), kWave, size_t(p) * 8, st>>>(
-        ix->n_rows, ix->n_dims, ix->log2_tile, p, ix->s_indptr, ix->s_indices, (const V*)ix->s_values, sc.freq,
-        sc.maxw, ix->iiib_fwd, ix->iiib_fwd_w, ix->iiib_cut);
+        ix->n_rows, ix->n_dims, ix->log2_tile, p, ix->s_indptr, ix->s_indices, (const V*)ix->s_values, ix->iiib_freq,
+        ix->iiib_maxw, ix->iiib_fwd, ix->iiib_fwd_w, ix->iiib_cut);
     k_bucket_starts<<<unsigned((n_keys + kBlock - 1) / kBlock), kBlock, 0, st>>>(n_keys, ix->iiib_cut);
     k_split_scatter<V><<<unsigned(ix->n_rows), kWave, 0, st>>>(ix->n_rows, ix->n_dims, ix->log2_tile, ix->s_indptr,
                                                                ix->iiib_fwd, ix->iiib_fwd_w, ix->offsets,
                                                                ix->iiib_cut, ix->rec_tmp);
     k_sort_small<<<unsigned((n_keys + kBlock - 1) / kBlock), kBlock, 0, st>>>(ix->offsets, n_keys, ix->rec_tmp,
-                                                                             sc.big, sc.n_big);
-    uint32_t h_big = 0;
-    KNNJ_HIP(hipMemcpyAsync(&h_big, sc.n_big, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    KNNJ_HIP(hipStreamSynchronize(st));
-    if (h_big > 0) {
-      k_sort_mid<<<h_big, kBlock, 0, st>>>(ix->offsets, sc.big, ix->rec_tmp);
-      k_sort_buckets<<<h_big, kBlock, kBucketSlots * sizeof(uint32_t), st>>>(ix->offsets, sc.big, ix->iiib_cut,
-                                                                              ix->rec_tmp, sc.out_tmp, ix->tile);
-    }
+                                                                             ix->iiib_big, n_big);
+    k_sort_mid<<<kSortGrid, kBlock, 0, st>>>(ix->offsets, ix->iiib_big, n_big, ix->rec_tmp);
+    k_sort_buckets<<<kSortGrid, kBlock, kBucketSlots * sizeof(uint32_t), st>>>(
+        ix->offsets, ix->iiib_big, n_big, ix->iiib_cut, ix->rec_tmp, ix->iiib_out_tmp, ix->tile);
     if (ix->nnz > 0) {
       const unsigned gf = unsigned((ix->nnz + kBlock - 1) / kBlock);
       if (ix->dtype == KNNJ_U8) k_finalize_iiib_u8<<<gf, kBlock, 0, st>>>(ix->rec_tmp, ix->nnz, ix->iiib_post);
@@ -542,8 +532,8 @@ static knnj_status build_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t
 
 template <typename V>
 static knnj_status join_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t r1, int32_t k,
-                              const knnj_join_opts* opt, int32_t* ids, void* scv, int32_t* cnt, uint64_t* slots,
-                              IiibScratch& sc, hipStream_t st) {
+                              const knnj_join_opts* opt, const int32_t* order, int32_t* ids, void* scv, int32_t* cnt,
+                              uint64_t* slots, hipStream_t st) {
   using S = typename ScoreOf<V>::T;
   S* scores = (S*)scv;
   const size_t smem = iiib_smem(ix, k);
@@ -553,26 +543,30 @@ static knnj_status join_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t 
   const int32_t drop = opt->level_drop;
   const int32_t filt = (opt->flags & KNNJ_FLAG_IIIB_BOUND) ? 1 : 0;
   const int64_t n = r1 - r0;
+  uint32_t* qcount = ix->iiib_small + 1;
   for (int pass = 0; pass < (opt->theta_seed ? 2 : 1); ++pass) {
     const bool fallback = pass == 1;
     if (fallback) {
-      KNNJ_HIP(hipMemsetAsync(sc.qcount, 0, sizeof(uint32_t), st));
+      knnj_status rc = launch_fill_u32(qcount, 1, 0u, st);
+      if (rc != KNNJ_OK) return rc;
       k_survivors<S><<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-          r0, n, k, opt->theta_seed, sc.seed2, ids, scores, cnt, sc.qlist, sc.qcount, opt->fallback_out, slots);
+          r0, n, k, opt->theta_seed, ix->iiib_seed2, ids, scores, cnt, ix->iiib_qlist, qcount, opt->fallback_out,
+          slots);
     }
     for (int32_t t = 0; t < ix->n_tiles; ++t) {
       k_iiib_tile<V><<<unsigned(n), kBlock, smem, st>>>(
-          t, ix->log2_tile, ix->n_dims, k, r0, fallback ? sc.qlist : nullptr, fallback ? sc.qcount : nullptr,
-          R->indptr, R->indices, (const V*)R->values, ix->offsets, ix->iiib_cut, P, ix->s_indptr, ix->iiib_fwd,
-          ix->iiib_fwd_w, fallback ? sc.seed2 : opt->theta_seed, drop, filt, ids, scores, cnt, slots);
+          t, ix->log2_tile, ix->n_dims, k, r0, fallback ? nullptr : order, fallback ? ix->iiib_qlist : nullptr,
+          fallback ? qcount : nullptr, R->indptr, R->indices, (const V*)R->values, ix->offsets, ix->iiib_cut, P,
+          ix->s_indptr, ix->iiib_fwd, ix->iiib_fwd_w, fallback ? ix->iiib_seed2 : opt->theta_seed, drop, filt, ids,
+          scores, cnt, slots);
     }
   }
   KNNJ_HIP(hipGetLastError());
   return KNNJ_OK;
 }
 
-knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids, void* scv,
-                        int32_t* cnt, uint64_t* slots, hipStream_t st) {
+knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, const int32_t* order,
+                        int32_t* ids, void* scv, int32_t* cnt, uint64_t* slots, hipStream_t st) {
   knnj_status rc = upload_tau();
   if (rc != KNNJ_OK) return rc;
   if (ix->dtype == KNNJ_U8 && ix->n_dims > kFwdMaxDimsU8)
@@ -584,21 +578,19 @@ knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join
   if (opt->level_drop < 0 || opt->level_drop >= kLevels) return fail(KNNJ_EINVAL, "level_drop must be in [0, 63]");
   const int64_t n_r = R->n_rows;
   const int64_t blk = opt->r_block_rows > 0 && opt->r_block_rows < n_r ? opt->r_block_rows : n_r;
-  IiibScratch sc;
-  rc = ensure(ix, sc, n_r);
+  if ((rc = ensure_iiib(ix, n_r)) != KNNJ_OK) return rc;
   for (int64_t r0 = 0; rc == KNNJ_OK && r0 < n_r; r0 += blk) {
     const int64_t r1 = r0 + blk < n_r ? r0 + blk : n_r;
+    // the longest-first order covers all of R: used when R is one block
+    const int32_t* ord = (r0 == 0 && r1 == n_r) ? order : nullptr;
     if (ix->dtype == KNNJ_U8) {
-      rc = build_block<uint8_t>(ix, R, r0, r1, sc, st);
-      if (rc == KNNJ_OK) rc = join_block<uint8_t>(ix, R, r0, r1, k, opt, ids, scv, cnt, slots, sc, st);
+      rc = build_block<uint8_t>(ix, R, r0, r1, st);
+      if (rc == KNNJ_OK) rc = join_block<uint8_t>(ix, R, r0, r1, k, opt, ord, ids, scv, cnt, slots, st);
     } else {
-      rc = build_block<float>(ix, R, r0, r1, sc, st);
-      if (rc == KNNJ_OK) rc = join_block<float>(ix, R, r0, r1, k, opt, ids, scv, cnt, slots, sc, st);
+      rc = build_block<float>(ix, R, r0, r1, st);
+      if (rc == KNNJ_OK) rc = join_block<float>(ix, R, r0, r1, k, opt, ord, ids, scv, cnt, slots, st);
     }
   }
-  // scratch is freed after the stream drains (hipFree may not wait for it)
-  (void)hipStreamSynchronize(st);
-  release(sc);
   return rc;
 }
 

@@ -191,34 +191,39 @@ __global__ void k_sort_small(const int64_t* __restrict__ offsets, int64_t n_keys
   for (int i = 0; i < len; ++i) rec[b + i] = a[i];
 }
 
-// Lists of 17..2048 entries: bitonic sort in local memory (ascending).
+// Lists of 17..2048 entries: bitonic sort in local memory (ascending).  The
+// grid strides over the queued lists (count on the device).
 __global__ void k_sort_mid(const int64_t* __restrict__ offsets, const int64_t* __restrict__ big,
-                           uint64_t* __restrict__ rec) {
+                           const uint32_t* __restrict__ n_big, uint64_t* __restrict__ rec) {
   __shared__ uint64_t buf[kMidSort];
-  const int64_t key = big[blockIdx.x];
-  const int64_t b = offsets[key], e = offsets[key + 1];
-  const int len = int(e - b);
-  if (len > kMidSort) return;
-  int p = 1;
-  while (p < len) p <<= 1;
-  for (int i = threadIdx.x; i < p; i += blockDim.x) buf[i] = i < len ? rec[b + i] : ~0ull;
-  __syncthreads();
-  for (int size = 2; size <= p; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < (p >> 1); i += blockDim.x) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = ((lo & size) == 0);
-        const uint64_t x = buf[lo], y = buf[hi];
-        if ((x > y) == up) {
-          buf[lo] = y;
-          buf[hi] = x;
+  const uint32_t nb = *n_big;
+  for (uint32_t item = blockIdx.x; item < nb; item += gridDim.x) {
+    const int64_t key = big[item];
+    const int64_t b = offsets[key], e = offsets[key + 1];
+    const int len = int(e - b);
+    if (len > kMidSort) continue;
+    int p = 1;
+    while (p < len) p <<= 1;
+    for (int i = threadIdx.x; i < p; i += blockDim.x) buf[i] = i < len ? rec[b + i] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= p; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < (p >> 1); i += blockDim.x) {
+          const int lo = 2 * i - (i & (stride - 1));
+          const int hi = lo + stride;
+          const bool up = ((lo & size) == 0);
+          const uint64_t x = buf[lo], y = buf[hi];
+          if ((x > y) == up) {
+            buf[lo] = y;
+            buf[hi] = x;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
+    for (int i = threadIdx.x; i < len; i += blockDim.x) rec[b + i] = buf[i];
+    __syncthreads();
   }
-  for (int i = threadIdx.x; i < len; i += blockDim.x) rec[b + i] = buf[i];
 }
 
 // Lists longer than 2048: s_local values of one list are distinct and below T,
@@ -387,7 +392,7 @@ knnj_status build_postings(Index* ix, const int64_t* indptr, const int32_t* indi
       break;
     }
     if (h_big > 0) {
-      k_sort_mid<<<h_big, kBlock, 0, st>>>(ix->offsets, big, ix->rec_tmp);
+      k_sort_mid<<<h_big, kBlock, 0, st>>>(ix->offsets, big, n_big, ix->rec_tmp);
       k_sort_large<<<h_big, kBlock, kSlotPass * sizeof(uint32_t), st>>>(ix->offsets, big, ix->rec_tmp, tmp2,
                                                                          ix->tile);
     }

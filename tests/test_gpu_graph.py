@@ -56,3 +56,54 @@ def test_graph_k1_and_k10_replays():
     rows = list(range(0, n, 50))
     want = oracle.bf_topk_rows(R, S, 10, rows)
     assert_exact(tuple(x[rows] for x in outs[10]), want, "graph replay k=10")
+
+
+def test_graph_learned_iiib_pipeline():
+    """Features -> MLP prediction -> seeded IIIB (survivor check + fallback pass),
+    with k = 1 and k = 10, all inside one captured graph; replays equal the
+    eager IIB result."""
+    S = synth.make("batched", "S", n_rows=30_000)
+    R = synth.make("batched", "R", n_rows=400)
+    T = synth.make("batched", "R", n_rows=3000)      # training queries (a larger draw; rows >= 400 unseen)
+    dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+    ix = kj.build_index(dS, tile_width=4096)
+    dT = kj.DeviceCSR.from_host(T.take_rows(range(400, 3000)))
+    _, tsc, tcnt = kj.knn_join(ix, dT, 10)
+    y = torch.where(tcnt == 10, tsc[:, 9].float(), torch.zeros_like(tcnt, dtype=torch.float32)).contiguous()
+    m = kj.Mlp(seed=5)
+    m.train(kj.Mlp.features(ix, dT), y, epochs=6, batch=256, lr=2e-3, tau=0.05, seed=3)
+    n = R.n_rows
+    ref = {k: [x.clone() for x in kj.knn_join(ix, dR, k)] for k in (1, 10)}
+    outs = {k: (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+                torch.empty((n, k), dtype=torch.int32, device="cuda"),
+                torch.empty(n, dtype=torch.int32, device="cuda")) for k in (1, 10)}
+    feats = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+    theta = torch.empty(n, dtype=torch.float32, device="cuda")
+    fb = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    # eager pass grows the library scratch and uploads constants before the capture
+    for k in (1, 10):
+        kj.knn_join(ix, dR, k, algo="iiib", theta_seed=m.predict(kj.Mlp.features(ix, dR)), bound_filter=True,
+                    level_drop=4, fallback_out=fb)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        feats.copy_(kj.Mlp.features(ix, dR))
+        theta.copy_(m.predict(feats))
+        for k in (1, 10):
+            kj.knn_join(ix, dR, k, algo="iiib", theta_seed=theta, bound_filter=True, level_drop=4, validate=False,
+                        fallback_out=fb, out=outs[k])
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in (1, 10):
+            for x in outs[k]:
+                x.fill_(-7)
+        kj.knn_join(ix, dR, 2)          # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in (1, 10):
+            for a, b in zip(outs[k], ref[k]):
+                assert torch.equal(a, b), (rep, k)
+    print("miss rate in the graph: %.3f" % float(fb.float().mean()), flush=True)
