@@ -1,0 +1,125 @@
+"""Autotuner for the join's launch parameters.
+
+Times candidate settings on the device (HIP events around real joins of a
+query sample) and keeps the fastest:
+
+* tile width T (rows of S per tile: the LDS score array and the list split),
+* schedule (one launch per tile, or the persistent work-queue launch),
+* for IIIB, the level drop of the refined variant.
+
+Results are cached in a JSON file keyed by the device architecture and a
+signature of the workload (S size, dimensions, value type, k, algorithm,
+query-sample cost), so a second call with the same signature does not time
+anything.  Cache path: $KNNJ_TUNE_CACHE or ~/.cache/knnj/tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Iterable, Optional
+
+import torch
+
+from . import knnj as kj
+
+DEFAULT_TILES = (2048, 4096, 8192)
+
+
+def _cache_path() -> str:
+    return os.environ.get("KNNJ_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "knnj", "tune.json"))
+
+
+def _load_cache() -> Dict:
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(tab: Dict) -> None:
+    p = _cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(tab, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def _arch() -> str:
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(p, "gcnArchName", p.name)
+
+
+def signature(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str) -> str:
+    nnz_s = int(S.indices.shape[0])
+    nnz_r = int(R_sample.indices.shape[0])
+    mean_r = nnz_r / max(1, R_sample.n_rows)
+    return "%s|S%d|nnz%d|D%d|%s|k%d|%s|r%.0f" % (_arch(), S.n_rows, int(math.log2(max(1, nnz_s))), S.n_dims,
+                                                 "u8" if S.dtype == kj.KNNJ_U8 else "f32", k, algo, mean_r)
+
+
+def _time(fn, reps: int = 2) -> float:
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", tiles: Iterable[int] = DEFAULT_TILES,
+         drops: Iterable[int] = (0, 2, 4, 6), use_cache: bool = True, verbose: bool = False) -> Dict:
+    """Fastest settings for joining queries like R_sample against S.
+
+    Returns {"tile_width", "persistent", "level_drop", "ms", "timings"}; the index
+    must then be built with tile_width.  R_sample should hold a few thousand
+    queries drawn like the real ones.
+    """
+    key = signature(S, R_sample, k, algo)
+    tab = _load_cache() if use_cache else {}
+    if key in tab:
+        return tab[key]
+    timings = []
+    best = None
+    out = (torch.empty((R_sample.n_rows, k), dtype=torch.int32, device="cuda"),
+           torch.empty((R_sample.n_rows, k), dtype=torch.int32 if S.dtype == kj.KNNJ_U8 else torch.float32,
+                       device="cuda"),
+           torch.empty(R_sample.n_rows, dtype=torch.int32, device="cuda"))
+    for t in tiles:
+        try:
+            ix = kj.build_index(S, tile_width=t)
+        except kj.KnnjError:
+            continue
+        cands = []
+        if algo == "iib":
+            cands = [dict(persistent=False), dict(persistent=True)]
+        else:
+            cands = [dict(bound_filter=True, level_drop=d) for d in drops]
+        for c in cands:
+            try:
+                ms = _time(lambda: kj.knn_join(ix, R_sample, k, algo=algo, validate=False, out=out, **c))
+            except kj.KnnjError:
+                continue
+            rec = {"tile_width": t, "ms": round(ms, 3), **c}
+            timings.append(rec)
+            if verbose:
+                print("autotune", rec, flush=True)
+            if best is None or ms < best["ms"]:
+                best = rec
+        ix.free()
+    if best is None:
+        raise RuntimeError("autotune: no candidate ran")
+    res = {"tile_width": best["tile_width"], "persistent": bool(best.get("persistent", False)),
+           "level_drop": int(best.get("level_drop", 0)), "bound_filter": bool(best.get("bound_filter", False)),
+           "ms": best["ms"], "timings": timings, "signature": key}
+    if use_cache:
+        tab = _load_cache()
+        tab[key] = res
+        _store_cache(tab)
+    return res

@@ -1,0 +1,41 @@
+"""The autotuner times real joins, picks the fastest tile width, and caches it;
+the tuned join stays exact."""
+import os
+
+import pytest
+
+import oracle
+import synth
+from helpers import assert_exact
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_1011_2807_amd as kj  # noqa: E402
+from paper_1011_2807_amd import autotune  # noqa: E402
+
+
+def test_autotune_picks_and_caches(tmp_path, monkeypatch):
+    monkeypatch.setenv("KNNJ_TUNE_CACHE", str(tmp_path / "tune.json"))
+    S = synth.make("medium", "S", n_rows=40_000)
+    R = synth.make("medium", "R", n_rows=400)
+    dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+    res = autotune.tune(dS, dR, 10, algo="iib", tiles=(1024, 4096), verbose=True)
+    assert res["tile_width"] in (1024, 4096)
+    assert len(res["timings"]) == 4
+    assert min(t["ms"] for t in res["timings"]) == res["ms"]
+    assert os.path.exists(tmp_path / "tune.json")
+    again = autotune.tune(dS, dR, 10, algo="iib", tiles=(1024, 4096))
+    assert again == res                       # served from the cache
+    ix = kj.build_index(dS, tile_width=res["tile_width"])
+    got = kj.knn_join(ix, dR, 10, persistent=res["persistent"])
+    torch.cuda.synchronize()
+    assert_exact(got, oracle.bf_topk(R, S, 10), "tuned IIB")
+    r2 = autotune.tune(dS, dR, 10, algo="iiib", tiles=(2048,), drops=(0, 4))
+    ix2 = kj.build_index(dS, tile_width=r2["tile_width"])
+    got = kj.knn_join(ix2, dR, 10, algo="iiib", bound_filter=r2["bound_filter"], level_drop=r2["level_drop"])
+    torch.cuda.synchronize()
+    assert_exact(got, oracle.bf_topk(R, S, 10), "tuned IIIB")
