@@ -129,7 +129,11 @@ typedef struct {
    * Any value keeps the result exact; it trades indexed postings for
    * completion work.  In [0, 63]. */
   int32_t level_drop;
-  int32_t reserved[5];
+  /* Optional upper bound on the longest row of R (0 = unknown).  Validation
+   * measures it; without validation 4096 is assumed.  Sizes IIIB's local copy of
+   * r when the dimensions are too many for a dense one. */
+  int32_t r_max_row_nnz;
+  int32_t reserved[4];
 } knnj_join_opts;
 
 /*

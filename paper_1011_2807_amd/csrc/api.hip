@@ -23,7 +23,7 @@ knnj_status launch_reduce_stats(const uint64_t* slots, uint64_t* out, hipStream_
 knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids, void* sc,
                        int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, const int32_t* order,
-                        int32_t* ids, void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
+                        int32_t max_r, int32_t* ids, void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k, const Sched& sch, int32_t* ids,
                                   void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
 knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
@@ -283,7 +283,8 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
   if (o.algo != KNNJ_IIB && o.algo != KNNJ_IIIB) return fail(KNNJ_EINVAL, "unknown algo");
   if (o.r_block_rows < 0) return fail(KNNJ_EINVAL, "r_block_rows must be >= 0");
   hipStream_t st = (hipStream_t)stream;
-  int32_t max_r = kMaxRowNnz;
+  if (o.r_max_row_nnz < 0 || o.r_max_row_nnz > kMaxRowNnz) return fail(KNNJ_EINVAL, "r_max_row_nnz out of range");
+  int32_t max_r = o.r_max_row_nnz > 0 ? o.r_max_row_nnz : kMaxRowNnz;
   if (!(o.flags & KNNJ_FLAG_NO_VALIDATE)) {
     if ((rc = validate_csr(R, ix->dev_err, st, &max_r)) != KNNJ_OK) return rc;
   }
@@ -311,7 +312,7 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
       rc = launch_iib(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
     }
   } else {
-    rc = launch_iiib(ix, R, k, &o, ix->js_order, ids, sc, cnt, slots, st);
+    rc = launch_iiib(ix, R, k, &o, ix->js_order, max_r, ids, sc, cnt, slots, st);
   }
   if (rc != KNNJ_OK) return rc;
   if (o.stats && (rc = launch_reduce_stats(slots, o.stats, st)) != KNNJ_OK) return rc;

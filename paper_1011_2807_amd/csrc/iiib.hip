@@ -292,6 +292,40 @@ __global__ void k_finalize_iiib_f32(const uint64_t* __restrict__ rec, int64_t n,
 }
 
 // ---------------------------------------------------------------- join
+// r as an open-addressing table in local memory: 2^lg slots of (d, weight),
+// empty slots hold d = -1; multiplicative hashing, linear probing.  The table
+// has at least twice as many slots as r has features, so probes stay short.
+template <typename RW>
+struct RHash {
+  int32_t* key;
+  RW* val;
+  int32_t lg;
+  __device__ __forceinline__ uint32_t slot(int32_t d) const { return (uint32_t(d) * 0x9e3779b1u) >> (32 - lg); }
+  __device__ __forceinline__ void insert(int32_t d, RW w) {
+    const uint32_t mask = (1u << lg) - 1u;
+    for (uint32_t h = slot(d);; h = (h + 1u) & mask) {
+      const int32_t prev = atomicCAS(&key[h], -1, d);
+      if (prev == -1 || prev == d) {
+        val[h] = w;
+        return;
+      }
+    }
+  }
+  __device__ __forceinline__ RW find(int32_t d) const {
+    const uint32_t mask = (1u << lg) - 1u;
+    for (uint32_t h = slot(d);; h = (h + 1u) & mask) {
+      const int32_t kk = key[h];
+      if (kk == d) return val[h];
+      if (kk == -1) return RW(0);
+    }
+  }
+};
+
+__host__ __device__ inline size_t r_region_bytes(int32_t n_dims, size_t wbytes, int32_t hash_log2) {
+  if (hash_log2 > 0) return (size_t(4) + (wbytes < 4 ? 4 : wbytes)) << hash_log2;
+  return (size_t(n_dims) * wbytes + 15) & ~size_t(15);
+}
+
 // IIIB on tile `tile`.  Queries: q0 + blockIdx.x, or (fallback pass) qlist[blockIdx.x]
 // for blockIdx.x < *qcount.  Local memory: acc[T] | r as a dense array over the
 // dimensions | stage.
@@ -302,8 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
     const V* __restrict__ r_val, const int64_t* __restrict__ offsets, const uint32_t* __restrict__ cut,
     Postings<V> P, const int64_t* __restrict__ s_ptr, const uint32_t* __restrict__ fwd,
     const float* __restrict__ fwd_w, const float* __restrict__ seed, int32_t level_drop, int32_t bound_filter,
-    int32_t* __restrict__ out_ids, typename ScoreOf<V>::T* __restrict__ out_sc, int32_t* __restrict__ out_cnt,
-    uint64_t* __restrict__ slots) {
+    int32_t r_hash_log2, int32_t* __restrict__ out_ids, typename ScoreOf<V>::T* __restrict__ out_sc,
+    int32_t* __restrict__ out_cnt, uint64_t* __restrict__ slots) {
   using S = typename ScoreOf<V>::T;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint32_t tmp[kBlock / kWave + 1];
@@ -316,17 +350,29 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
   }
   const int T = 1 << log2_tile;
   S* acc = reinterpret_cast<S*>(smem);
+  // r for the completion: a dense array over the dimensions, or (large n_dims,
+  // r_hash_log2 > 0) an open-addressing table keyed by d in local memory
   using RW = typename std::conditional<sizeof(V) == 1, uint8_t, float>::type;
-  const size_t rbytes = (size_t(n_dims) * sizeof(RW) + 15) & ~size_t(15);
+  const size_t rbytes = r_region_bytes(n_dims, sizeof(RW), r_hash_log2);
   RW* rdense = reinterpret_cast<RW*>(smem + size_t(T) * 4);
+  RHash<RW> rh{reinterpret_cast<int32_t*>(smem + size_t(T) * 4),
+               reinterpret_cast<RW*>(smem + size_t(T) * 4 + (size_t(4) << (r_hash_log2 > 0 ? r_hash_log2 : 0))),
+               r_hash_log2};
   char* stage = smem + size_t(T) * 4 + rbytes;
   const int64_t s_base = int64_t(tile) << log2_tile;
 
   for (int i = threadIdx.x; i < T / 4; i += kBlock) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
-  for (size_t i = threadIdx.x; i < rbytes / 16; i += kBlock) reinterpret_cast<uint4*>(rdense)[i] = make_uint4(0, 0, 0, 0);
+  if (r_hash_log2 > 0) {
+    for (int i = threadIdx.x; i < (1 << r_hash_log2); i += kBlock) rh.key[i] = -1;
+  } else {
+    for (size_t i = threadIdx.x; i < rbytes / 16; i += kBlock) reinterpret_cast<uint4*>(rdense)[i] = make_uint4(0, 0, 0, 0);
+  }
   __syncthreads();
   const int64_t rb = r_ptr[q], re = r_ptr[q + 1];
-  for (int64_t j = rb + threadIdx.x; j < re; j += kBlock) rdense[r_idx[j]] = r_val[j];
+  for (int64_t j = rb + threadIdx.x; j < re; j += kBlock) {
+    if (r_hash_log2 > 0) rh.insert(r_idx[j], RW(r_val[j]));
+    else rdense[r_idx[j]] = r_val[j];
+  }
 
   // threshold: the running pruneScore, raised by the seed if one is given
   const int cnt = out_cnt[q];
@@ -379,8 +425,13 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
       for (; e < e1; ++e) {
         const uint32_t f = fwd[e];
         if ((f & 63u) >= lambda) break;
-        if constexpr (sizeof(V) == 1) sum += uint32_t(rdense[f >> 14]) * ((f >> 6) & 0xffu);
-        else sum += rdense[f >> 6] * fwd_w[e];
+        if constexpr (sizeof(V) == 1) {
+          const uint32_t d = f >> 14;
+          sum += uint32_t(r_hash_log2 > 0 ? rh.find(int32_t(d)) : rdense[d]) * ((f >> 6) & 0xffu);
+        } else {
+          const uint32_t d = f >> 6;
+          sum += (r_hash_log2 > 0 ? rh.find(int32_t(d)) : rdense[d]) * fwd_w[e];
+        }
       }
       acc[a] = v + sum;
       ++n_cand;
@@ -487,9 +538,18 @@ static knnj_status ensure_iiib(Index* ix, int64_t n_r) {
   return KNNJ_OK;
 }
 
-static size_t iiib_smem(const Index* ix, int k) {
-  const size_t rbytes = (size_t(ix->n_dims) * (ix->dtype == KNNJ_U8 ? 1 : 4) + 15) & ~size_t(15);
-  return tile_smem_bytes(ix->tile, k) + rbytes;
+// A dense copy of r is used when it takes at most 32 KB; otherwise a hash table
+// with 2^lg >= 2 * (longest row of R) slots.
+static int32_t r_hash_log2(const Index* ix, int32_t max_r) {
+  const size_t wb = ix->dtype == KNNJ_U8 ? 1 : 4;
+  if (size_t(ix->n_dims) * wb <= 32768) return 0;
+  int32_t lg = 4;
+  while ((1 << lg) < 2 * (max_r > 0 ? max_r : 1)) ++lg;
+  return lg;
+}
+
+static size_t iiib_smem(const Index* ix, int k, int32_t hash_lg) {
+  return tile_smem_bytes(ix->tile, k) + r_region_bytes(ix->n_dims, ix->dtype == KNNJ_U8 ? 1 : 4, hash_lg);
 }
 
 // Builds the IIIB index of R rows [r0, r1) into ix->iiib_*.  Enqueues kernels only.
@@ -532,11 +592,11 @@ static knnj_status build_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t
 
 template <typename V>
 static knnj_status join_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t r1, int32_t k,
-                              const knnj_join_opts* opt, const int32_t* order, int32_t* ids, void* scv, int32_t* cnt,
-                              uint64_t* slots, hipStream_t st) {
+                              const knnj_join_opts* opt, const int32_t* order, int32_t hash_lg, int32_t* ids,
+                              void* scv, int32_t* cnt, uint64_t* slots, hipStream_t st) {
   using S = typename ScoreOf<V>::T;
   S* scores = (S*)scv;
-  const size_t smem = iiib_smem(ix, k);
+  const size_t smem = iiib_smem(ix, k, hash_lg);
   Postings<V> P;
   if constexpr (sizeof(V) == 1) P = Postings<V>{reinterpret_cast<const uint4*>(ix->iiib_post)};
   else P = Postings<V>{reinterpret_cast<const uint2*>(ix->iiib_post_s), reinterpret_cast<const float4*>(ix->iiib_post_w)};
@@ -557,8 +617,8 @@ static knnj_status join_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t 
       k_iiib_tile<V><<<unsigned(n), kBlock, smem, st>>>(
           t, ix->log2_tile, ix->n_dims, k, r0, fallback ? nullptr : order, fallback ? ix->iiib_qlist : nullptr,
           fallback ? qcount : nullptr, R->indptr, R->indices, (const V*)R->values, ix->offsets, ix->iiib_cut, P,
-          ix->s_indptr, ix->iiib_fwd, ix->iiib_fwd_w, fallback ? ix->iiib_seed2 : opt->theta_seed, drop, filt, ids,
-          scores, cnt, slots);
+          ix->s_indptr, ix->iiib_fwd, ix->iiib_fwd_w, fallback ? ix->iiib_seed2 : opt->theta_seed, drop, filt,
+          hash_lg, ids, scores, cnt, slots);
     }
   }
   KNNJ_HIP(hipGetLastError());
@@ -566,15 +626,16 @@ static knnj_status join_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t 
 }
 
 knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, const int32_t* order,
-                        int32_t* ids, void* scv, int32_t* cnt, uint64_t* slots, hipStream_t st) {
+                        int32_t max_r, int32_t* ids, void* scv, int32_t* cnt, uint64_t* slots, hipStream_t st) {
   knnj_status rc = upload_tau();
   if (rc != KNNJ_OK) return rc;
   if (ix->dtype == KNNJ_U8 && ix->n_dims > kFwdMaxDimsU8)
     return fail(KNNJ_EUNSUPPORTED, "IIIB supports at most 2^18 dimensions for uint8 data");
   int max_smem = 0;
   KNNJ_HIP(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device));
-  if (iiib_smem(ix, k) > size_t(max_smem))
-    return fail(KNNJ_EUNSUPPORTED, "IIIB: tile accumulators plus a dense copy of r exceed workgroup local memory");
+  const int32_t hash_lg = r_hash_log2(ix, max_r);
+  if (iiib_smem(ix, k, hash_lg) > size_t(max_smem))
+    return fail(KNNJ_EUNSUPPORTED, "IIIB: tile accumulators plus the copy of r exceed workgroup local memory");
   if (opt->level_drop < 0 || opt->level_drop >= kLevels) return fail(KNNJ_EINVAL, "level_drop must be in [0, 63]");
   const int64_t n_r = R->n_rows;
   const int64_t blk = opt->r_block_rows > 0 && opt->r_block_rows < n_r ? opt->r_block_rows : n_r;
@@ -585,10 +646,10 @@ knnj_status launch_iiib(Index* ix, const knnj_csr* R, int32_t k, const knnj_join
     const int32_t* ord = (r0 == 0 && r1 == n_r) ? order : nullptr;
     if (ix->dtype == KNNJ_U8) {
       rc = build_block<uint8_t>(ix, R, r0, r1, st);
-      if (rc == KNNJ_OK) rc = join_block<uint8_t>(ix, R, r0, r1, k, opt, ord, ids, scv, cnt, slots, st);
+      if (rc == KNNJ_OK) rc = join_block<uint8_t>(ix, R, r0, r1, k, opt, ord, hash_lg, ids, scv, cnt, slots, st);
     } else {
       rc = build_block<float>(ix, R, r0, r1, st);
-      if (rc == KNNJ_OK) rc = join_block<float>(ix, R, r0, r1, k, opt, ord, ids, scv, cnt, slots, st);
+      if (rc == KNNJ_OK) rc = join_block<float>(ix, R, r0, r1, k, opt, ord, hash_lg, ids, scv, cnt, slots, st);
     }
   }
   return rc;

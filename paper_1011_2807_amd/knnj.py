@@ -46,7 +46,7 @@ class _IndexOpts(ctypes.Structure):
 class _JoinOpts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("flags", ctypes.c_uint32), ("r_block_rows", ctypes.c_int64),
                 ("theta_seed", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("fallback_out", ctypes.c_void_p),
-                ("level_drop", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("level_drop", ctypes.c_int32), ("r_max_row_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class _IndexInfo(ctypes.Structure):
@@ -195,7 +195,7 @@ def _outputs(n: int, k: int, dtype: int, out):
 def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows: int = 0,
              theta_seed: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
              fallback_out: Optional[torch.Tensor] = None, validate: bool = True, bound_filter: bool = False,
-             level_drop: int = 0, persistent: bool = False, out=None, stream=None):
+             level_drop: int = 0, persistent: bool = False, r_max_row_nnz: int = 0, out=None, stream=None):
     """Exact top-k of every row of R against the indexed S.
 
     Returns (ids int32[n,k], scores int32|float32[n,k], count int32[n]) on the device.
@@ -212,6 +212,7 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     o.flags = ((0 if validate else KNNJ_FLAG_NO_VALIDATE) | (KNNJ_FLAG_IIIB_BOUND if bound_filter else 0) |
                (KNNJ_FLAG_PERSISTENT if persistent else 0))
     o.level_drop = int(level_drop)
+    o.r_max_row_nnz = int(r_max_row_nnz)
     o.r_block_rows = int(r_block_rows)
     if theta_seed is not None:
         assert theta_seed.dtype == torch.float32 and theta_seed.is_cuda and theta_seed.numel() == R.n_rows

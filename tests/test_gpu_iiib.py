@@ -132,3 +132,19 @@ def test_f32_iiib_within_tolerance():
     got = kj.knn_join(ix, _dev(R), 50, algo="iiib")
     torch.cuda.synchronize()
     assert_f32_close(got, R, S, range(R.n_rows), what="f32 IIIB")
+
+
+@pytest.mark.parametrize("values,n_dims", [("f32", 20_000), ("u8", 50_000)])
+def test_iiib_hashed_r_for_many_dimensions(values, n_dims):
+    """Dimensions too many for a dense local copy of r: IIIB completes candidates
+    through the local hash table of r's features."""
+    S = synth.draw(601, 12_000, n_dims, (30, 300), features="zipf", zipf_s=1.05, values=values)
+    R = synth.draw(602, 60, n_dims, (30, 300), features="zipf", zipf_s=1.05, values=values)
+    ix = kj.build_index(_dev(S), tile_width=4096)
+    for validate in (True, False):
+        got = kj.knn_join(ix, _dev(R), 50 if values == "f32" else 10, algo="iiib", validate=validate)
+        torch.cuda.synchronize()
+        if values == "f32":
+            assert_f32_close(got, R, S, range(R.n_rows), what="f32 hashed IIIB")
+        else:
+            assert_exact(got, oracle.bf_topk(R, S, 10), "u8 hashed IIIB")
