@@ -114,6 +114,12 @@ def main():
     if a.workload == "batched":
         return run_batched(a)
     wl = synth.WORKLOADS[a.workload]
+    if a.workload == "fp32" and (a.n_s or wl["n_s"]) > 1_000_000:
+        # a run at the full size of this workload (10M vectors, 100K dimensions) made a
+        # device memory fault whose cause is not found yet; smaller S only
+        print("bench.py: the fp32 workload runs with --n-s <= 1,000,000 until its full-size fault is explained",
+              file=sys.stderr)
+        sys.exit(2)
     k = a.k or wl["k"][-1]
     n_r = a.n_r or wl["n_r"]
     n_s = a.n_s or wl["n_s"]
