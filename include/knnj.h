@@ -84,7 +84,13 @@ typedef struct {
    * workgroup's local memory (the block B_s of Algorithm 1).  0 selects the
    * default; otherwise a power of two in [256, 65536]. */
   int32_t tile_width;
-  int32_t reserved[7];
+  /* uint8 data only: also keep the dense_head dimensions with the longest lists
+   * as a dense block per tile; the IIB join then computes their part of every
+   * score with byte dot products and walks only the other lists (same exact
+   * result; pays off when a few dimensions hold most postings).  0 = off;
+   * otherwise a multiple of 16 in [16, 256]. */
+  int32_t dense_head;
+  int32_t reserved[6];
 } knnj_index_opts;
 
 /* Flags of knnj_join_opts.flags */
@@ -98,6 +104,8 @@ typedef struct {
  * With this flag: one persistent launch per tile whose resident workgroups take
  * queries, in the same order, from a device counter.  Same results. */
 #define KNNJ_FLAG_PERSISTENT 4u
+/* Ignore the index's dense head: walk every list (the plain Algorithm 3 walk). */
+#define KNNJ_FLAG_NO_DENSE_HEAD 8u
 
 /* Counters accumulated into knnj_join_opts.stats (device uint64[KNNJ_STAT_COUNT]). */
 enum {
@@ -156,7 +164,7 @@ typedef struct {
   int32_t tile_width;
   int32_t n_tiles;
   int32_t max_row_nnz;
-  int32_t reserved;
+  int32_t dense_head;
 } knnj_index_info;
 
 knnj_status knnj_index_info_get(const knnj_index* ix, knnj_index_info* out);

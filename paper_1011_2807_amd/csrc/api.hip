@@ -29,6 +29,10 @@ knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k,
 knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 knnj_status launch_lpt_order(int64_t n, const int64_t* r_ptr, const int32_t* r_idx, const uint32_t* list_len,
                              uint32_t* bucket, uint32_t* hist, int32_t* order, hipStream_t st);
+knnj_status build_head(Index* ix, hipStream_t st);
+knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids,
+                            void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
+size_t head_smem_bytes(int tile, int k, int H);
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st);
 size_t tile_smem_bytes(int tile);
@@ -58,6 +62,12 @@ static void free_index(Index* ix) {
   (void)hipFree(ix->post_s);
   (void)hipFree(ix->post_w);
   (void)hipFree(ix->list_len);
+  (void)hipFree(ix->head_pos);
+  (void)hipFree(ix->head_blk);
+  (void)hipFree(ix->hj_cnt);
+  (void)hipFree(ix->hj_d);
+  (void)hipFree(ix->hj_w);
+  (void)hipFree(ix->hj_rh);
   (void)hipFree(ix->s_indptr);
   (void)hipFree(ix->s_indices);
   (void)hipFree(ix->s_values);
@@ -115,6 +125,13 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
   if (tile_smem_bytes(tile) > size_t(max_smem))
     return fail(KNNJ_EUNSUPPORTED, "tile_width too large for this device's local memory (" +
                                        std::to_string(max_smem) + " bytes per workgroup)");
+  const int head = opt ? opt->dense_head : 0;
+  if (head != 0) {
+    if (S->dtype != KNNJ_U8) return fail(KNNJ_EUNSUPPORTED, "dense_head needs uint8 data");
+    if (head < 16 || head > 256 || (head % 16)) return fail(KNNJ_EINVAL, "dense_head must be a multiple of 16 in [16, 256]");
+    if (head_smem_bytes(tile, 1, head) > size_t(max_smem))
+      return fail(KNNJ_EUNSUPPORTED, "tile_width too large for the dense-head join's local memory");
+  }
   Index* ix = new Index();
   ix->device = dev;
   ix->n_rows = S->n_rows;
@@ -168,6 +185,13 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
     free_index(ix);
     return rc;
   }
+  if (head > 0) {
+    ix->head_h = head;
+    if ((rc = build_head(ix, st)) != KNNJ_OK) {
+      free_index(ix);
+      return rc;
+    }
+  }
   *out = reinterpret_cast<knnj_index*>(ix);
   return KNNJ_OK;
 }
@@ -183,6 +207,7 @@ knnj_status knnj_index_info_get(const knnj_index* h, knnj_index_info* out) {
   out->tile_width = ix->tile;
   out->n_tiles = ix->n_tiles;
   out->max_row_nnz = ix->max_row_nnz;
+  out->dense_head = ix->head_h;
   return KNNJ_OK;
 }
 
@@ -308,6 +333,10 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
       if ((rc = reset_sched(ix, 0, st)) != KNNJ_OK) return rc;
       rc = launch_iib_persistent(ix, R, k, make_sched(ix, R->n_rows, ix->js_order, nullptr, 0), ids, sc, cnt, slots,
                                  st);
+    } else if (ix->head_h > 0 && !(o.flags & KNNJ_FLAG_NO_DENSE_HEAD) &&
+               head_smem_bytes(ix->tile, k, ix->head_h) <= size_t(device_max_smem(ix->device))) {
+      // (a k too large for the dense-head kernel's local memory takes the plain walk)
+      rc = launch_iib_head(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
     } else {
       rc = launch_iib(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
     }

@@ -46,6 +46,19 @@ struct Index {
   uint16_t* post_s = nullptr;
   float* post_w = nullptr;
   uint32_t* list_len = nullptr;  // |I_d| over all of S
+  // dense head (optional): the head_h dimensions with the longest lists, per tile
+  // as [head_h / 16][T][16] bytes
+  int32_t head_h = 0;
+  int32_t* head_pos = nullptr;   // rank of d among the head dimensions, or -1
+  uint8_t* head_blk = nullptr;
+  // join scratch of the dense-head join (grow-only): per query, its tail
+  // features moved to the front of its CSR row (d, w) and their count, and its
+  // head weights as a dense row of head_h bytes
+  int64_t hj_cap_q = 0, hj_cap_nnz = 0;
+  uint32_t* hj_cnt = nullptr;
+  int32_t* hj_d = nullptr;
+  uint8_t* hj_w = nullptr;
+  uint8_t* hj_rh = nullptr;
   // private copy of S (forward lists), used by the IIIB refinement
   int64_t* s_indptr = nullptr;
   int32_t* s_indices = nullptr;

@@ -42,30 +42,18 @@ struct Postings<float> {
   const float4* w;
 };
 
-// Stage the lists (tile, d) of features [cb, cb + n) of one query; returns the
-// number of 4-entry groups in their concatenation.  Thread t stages list t.
-// With a cut table (IIIB) only the first cut[key * kLevels + lambda] entries of
-// list `key` are staged: the entries whose level is >= lambda.
-template <typename V, typename S>
-__device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int64_t key0, const int32_t* r_idx,
-                                                const V* r_val, int64_t cb, int n, const int64_t* offsets,
-                                                const uint32_t* cut = nullptr, uint32_t lambda = 0) {
+// Write the list table of n lists (thread j < n describes list j: first entry
+// `beg`, `len` entries, weight w) and return the number of 4-entry groups in
+// the lists' concatenation.  Ends with a barrier.
+template <typename S>
+__device__ __forceinline__ uint32_t stage_write(char* stage, uint32_t* tmp, int n, int64_t beg, uint32_t len, S w) {
   uint32_t* pre = reinterpret_cast<uint32_t*>(stage + kPreOff);
   int64_t* cbase = reinterpret_cast<int64_t*>(stage + kCbOff);
   uint32_t* meta = reinterpret_cast<uint32_t*>(stage + kMetaOff);
   S* w_of = reinterpret_cast<S*>(stage + kWOff);
   const int j = threadIdx.x;
-  uint32_t groups = 0, len = 0, off = 0;
-  int64_t beg = 0;
-  S w = S(0);
-  if (j < n) {
-    const int64_t key = key0 + r_idx[cb + j];
-    beg = offsets[key];
-    len = cut ? cut[key * kLevels + lambda] : uint32_t(offsets[key + 1] - beg);
-    off = uint32_t(beg & 3);
-    groups = len ? uint32_t(((beg + len + 3) >> 2) - (beg >> 2)) : 0u;
-    w = S(r_val[cb + j]);
-  }
+  const uint32_t off = uint32_t(beg & 3);
+  const uint32_t groups = len ? uint32_t(((beg + len + 3) >> 2) - (beg >> 2)) : 0u;
   uint32_t total;
   const uint32_t ex = block_exclusive_scan(groups, tmp, &total);
   if (j < n) {
@@ -79,15 +67,39 @@ __device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int6
   return total;
 }
 
+// Stage the lists (tile, d) of features [cb, cb + n) of one query; returns the
+// number of 4-entry groups in their concatenation.  Thread t stages list t.
+// With a cut table (IIIB) only the first cut[key * kLevels + lambda] entries of
+// list `key` are staged: the entries whose level is >= lambda.
+template <typename V, typename S>
+__device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int64_t key0, const int32_t* r_idx,
+                                                const V* r_val, int64_t cb, int n, const int64_t* offsets,
+                                                const uint32_t* cut = nullptr, uint32_t lambda = 0) {
+  const int j = threadIdx.x;
+  uint32_t len = 0;
+  int64_t beg = 0;
+  S w = S(0);
+  if (j < n) {
+    const int64_t key = key0 + r_idx[cb + j];
+    beg = offsets[key];
+    len = cut ? cut[key * kLevels + lambda] : uint32_t(offsets[key + 1] - beg);
+    w = S(r_val[cb + j]);
+  }
+  return stage_write<S>(stage, tmp, n, beg, len, w);
+}
+
 // Walk the staged concatenation.  The workgroup is split into teams of 8 lanes;
 // team t takes the t-th of 32 contiguous ranges of groups and its lanes take
 // groups start + i, start + i + 8, ...  A group is one aligned 16-byte load of
 // four entries, so one team load is one 128-byte line.  Entries inside the
 // list's range are added into acc (swizzled slots) with local-memory atomics.
 // A lane only steps over the lists inside its team's range.
+// kMulti (uint8 only): the lists belong to several queries; a list's weight
+// word is (slot << 8) | w and its scores go to acc + (slot << log2_tile).
 constexpr int kTeam = 8;
-template <typename V, typename S>
-__device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P) {
+template <typename V, typename S, bool kMulti = false>
+__device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P,
+                                           int log2_tile = 0) {
   constexpr int U = 4;
   const uint32_t* pre = reinterpret_cast<const uint32_t*>(stage + kPreOff);
   const int64_t* cbase = reinterpret_cast<const int64_t*>(stage + kCbOff);
@@ -148,9 +160,17 @@ __device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_list
     for (int u = 0; u < U; ++u) {
       if constexpr (sizeof(V) == 1) {
         const uint32_t x[4] = {e[u].x, e[u].y, e[u].z, e[u].w};
+        if constexpr (kMulti) {
+          S* a = acc + (size_t(ww[u] >> 8) << log2_tile);
+          const uint32_t wq = ww[u] & 0xffu;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[swz(x[i] >> 16)], ww[u] * ((x[i] >> 8) & 0xffu));
+          for (int i = 0; i < 4; ++i)
+            if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&a[swz(x[i] >> 16)], wq * ((x[i] >> 8) & 0xffu));
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[swz(x[i] >> 16)], ww[u] * ((x[i] >> 8) & 0xffu));
+        }
       } else {
         const uint32_t sx[4] = {es[u].x & 0xffffu, es[u].x >> 16, es[u].y & 0xffffu, es[u].y >> 16};
         const float wx[4] = {ew[u].x, ew[u].y, ew[u].z, ew[u].w};

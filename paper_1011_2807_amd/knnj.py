@@ -23,6 +23,7 @@ KNNJ_IIB, KNNJ_IIIB = 0, 1
 KNNJ_FLAG_NO_VALIDATE = 1
 KNNJ_FLAG_IIIB_BOUND = 2
 KNNJ_FLAG_PERSISTENT = 4
+KNNJ_FLAG_NO_DENSE_HEAD = 8
 STAT_POSTINGS, STAT_COMPLETION, STAT_CANDIDATES, STAT_FALLBACKS, STAT_COUNT = 0, 1, 2, 3, 8
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "EUNSUPPORTED"}
 
@@ -40,7 +41,7 @@ class _CSR(ctypes.Structure):
 
 
 class _IndexOpts(ctypes.Structure):
-    _fields_ = [("tile_width", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("tile_width", ctypes.c_int32), ("dense_head", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class _JoinOpts(ctypes.Structure):
@@ -52,7 +53,7 @@ class _JoinOpts(ctypes.Structure):
 class _IndexInfo(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_dims", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("tile_width", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
-                ("max_row_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_row_nnz", ctypes.c_int32), ("dense_head", ctypes.c_int32)]
 
 
 _lib = None
@@ -157,6 +158,10 @@ class Index:
     def n_tiles(self) -> int:
         return int(self.info.n_tiles)
 
+    @property
+    def dense_head(self) -> int:
+        return int(self.info.dense_head)
+
     def list_lengths(self, stream=None) -> torch.Tensor:
         """|I_d| for every dimension (device int32)."""
         out = torch.empty(self.n_dims, dtype=torch.int32, device="cuda")
@@ -175,10 +180,12 @@ class Index:
             pass
 
 
-def build_index(S: DeviceCSR, tile_width: int = 0, stream=None) -> Index:
+def build_index(S: DeviceCSR, tile_width: int = 0, dense_head: int = 0, stream=None) -> Index:
+    """dense_head: uint8 data only; keep that many longest-list dimensions as dense
+    per-tile blocks for the IIB join (0 = off)."""
     lib = load_library()
     h = ctypes.c_void_p()
-    opts = _IndexOpts(int(tile_width))
+    opts = _IndexOpts(int(tile_width), int(dense_head))
     c = S._c()
     _check(lib.knnj_build_index(ctypes.byref(c), ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Index(h, S)
@@ -195,7 +202,8 @@ def _outputs(n: int, k: int, dtype: int, out):
 def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows: int = 0,
              theta_seed: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
              fallback_out: Optional[torch.Tensor] = None, validate: bool = True, bound_filter: bool = False,
-             level_drop: int = 0, persistent: bool = False, r_max_row_nnz: int = 0, out=None, stream=None):
+             level_drop: int = 0, persistent: bool = False, r_max_row_nnz: int = 0, dense_head: bool = True,
+             out=None, stream=None):
     """Exact top-k of every row of R against the indexed S.
 
     Returns (ids int32[n,k], scores int32|float32[n,k], count int32[n]) on the device.
@@ -204,13 +212,14 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     counters (added to).  fallback_out: optional uint8[n] device tensor.
     bound_filter / level_drop: IIIB refinements (see knnj.h); results stay exact.
     persistent: one persistent launch per S tile with a device work queue (IIB).
+    dense_head: use the index's dense head if it has one (IIB); False walks every list.
     """
     lib = load_library()
     ids, sc, cnt = _outputs(R.n_rows, k, index.dtype, out)
     o = _JoinOpts()
     o.algo = KNNJ_IIIB if algo == "iiib" else KNNJ_IIB
     o.flags = ((0 if validate else KNNJ_FLAG_NO_VALIDATE) | (KNNJ_FLAG_IIIB_BOUND if bound_filter else 0) |
-               (KNNJ_FLAG_PERSISTENT if persistent else 0))
+               (KNNJ_FLAG_PERSISTENT if persistent else 0) | (0 if dense_head else KNNJ_FLAG_NO_DENSE_HEAD))
     o.level_drop = int(level_drop)
     o.r_max_row_nnz = int(r_max_row_nnz)
     o.r_block_rows = int(r_block_rows)
