@@ -6,8 +6,12 @@ index and both inputs already resident in device memory.  The default
 workload is the medium one: |R| = 100,000, |S| = 1,000,000, D = 10,000,
 nnz U[50,200], Zipf(1.1) feature ids, uint8 values, k = 10.
 
-The headline `value` is the IIB join (Algorithm 3).  Beside it, on the same
-queries and each checked identical to the IIB output:
+The headline `value` is the IIB join (Algorithm 3) on uint8 data with a dense
+head: the 128 dimensions with the longest lists are kept as dense per-tile byte
+blocks, scored with byte dot products, and only the other lists are walked
+(exact; --dense-head 0 gives the plain list walk).  Beside it, on the same
+queries and each checked identical to the headline output:
+  iib_plain_walk  the same index walked list by list
   iiib.plain    Algorithm 4 as printed (split at the running threshold, every
                 candidate completed)
   iiib.refined  the same plus the bound-filtered completion and a 4-step level
@@ -49,6 +53,9 @@ def _args():
     ap.add_argument("--n-train", type=int, default=0, help="training queries of the learned seed")
     ap.add_argument("--no-iiib", action="store_true", help="skip the IIIB / learned-seed legs")
     ap.add_argument("--persistent", action="store_true", help="IIB: persistent per-tile launches with a work queue")
+    ap.add_argument("--dense-head", type=int, default=-1,
+                    help="dimensions kept as dense per-tile blocks (u8 only; -1 = 128 for u8, 0 = plain walk)")
+    ap.add_argument("--tiles-per-launch", type=int, default=4, help="dense-head join: S tiles per launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=4, help="queries checked against the oracle after timing")
@@ -58,11 +65,11 @@ def _args():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("common.hpp", "select.hpp", "walk.hpp", "join.hip")
+KERNEL_SOURCES = ("common.hpp", "select.hpp", "walk.hpp", "join.hip", "head.hip")
 
 
 def _kernel_hash() -> str:
-    """Hash of the sources the IIB tile kernel is built from."""
+    """Hash of the sources the IIB tile kernels are built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1011_2807_amd", "csrc")
     for f in KERNEL_SOURCES:
@@ -147,13 +154,18 @@ def main():
     torch.cuda.set_device(dev)
     dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
     torch.cuda.synchronize()
+    head = a.dense_head if a.dense_head >= 0 else (128 if S.values.dtype == np.uint8 else 0)
+    if a.persistent:
+        head = 0
     tb = time.time()
-    ix = kj.build_index(dS, tile_width=a.tile)
+    ix = kj.build_index(dS, tile_width=a.tile or (2048 if head else 0), dense_head=head)
     torch.cuda.synchronize()
     t_build = time.time() - tb
-    _log("index built in %.3fs (T=%d, %d tiles)" % (t_build, ix.tile_width, ix.n_tiles))
+    _log("index built in %.3fs (T=%d, %d tiles, dense head %d)" % (t_build, ix.tile_width, ix.n_tiles, head))
     stream = torch.cuda.current_stream()
     sdt = torch.int32 if S.values.dtype == np.uint8 else torch.float32
+    G = a.tiles_per_launch
+    jkw = dict(persistent=a.persistent, tiles_per_launch=G)
 
     def outs():
         return (torch.empty((n_r, k), dtype=torch.int32, device=dev), torch.empty((n_r, k), dtype=sdt, device=dev),
@@ -162,16 +174,16 @@ def main():
     out = outs()
     stats = torch.zeros(8, dtype=torch.int64, device=dev)
     for w in range(max(1, a.warmup)):
-        kj.knn_join(ix, dR, k, stats=stats if w == 0 else None, validate=(w == 0), out=out, persistent=a.persistent)
+        kj.knn_join(ix, dR, k, stats=stats if w == 0 else None, validate=(w == 0), out=out, **jkw)
         torch.cuda.synchronize()
         _log("warmup %d done" % w)
-    walked = int(stats[kj.STAT_POSTINGS].item())
+    walked_tail = int(stats[kj.STAT_POSTINGS].item())
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
     for s in range(a.steps):
-        kj.knn_join(ix, dR, k, validate=False, out=out, stream=stream, persistent=a.persistent)
+        kj.knn_join(ix, dR, k, validate=False, out=out, stream=stream, **jkw)
         _log("step %d launched" % s)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -179,23 +191,55 @@ def main():
     _log("timed %d steps: %.1f ms/step" % (a.steps, ms))
     qps = n_r / (ms / 1e3)
     entry_bytes = 4 if S.values.dtype == np.uint8 else 6
+    walk = None
+    walked = walked_tail
+    if head:
+        # the same index walked list by list (Algorithm 3's accumulation with no
+        # dense head): the comparison leg, and the count of every posting the
+        # method processes per step
+        o2 = outs()
+        st2 = torch.zeros(8, dtype=torch.int64, device=dev)
+        kj.knn_join(ix, dR, k, out=o2, stats=st2, validate=False, dense_head=False)
+        torch.cuda.synchronize()
+        walked = int(st2[kj.STAT_POSTINGS].item())
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        kj.knn_join(ix, dR, k, out=o2, validate=False, dense_head=False, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        walk = {"queries_per_s": round(n_r / (t / 1e3), 1), "ms": round(t, 2), "tile_width": ix.tile_width,
+                "identical_to_dense_head": all(torch.equal(x, y) for x, y in zip(o2, out)),
+                "speedup_of_dense_head": round(t / ms, 3)}
+        _log("plain walk", json.dumps(walk))
+        del o2
     eps = walked / (ms / 1e3)
     gbps = eps * entry_bytes / 1e9
-    # dominant kernel: one launch per S tile; its average launch duration is the
-    # step time over the launches (the only other launch per step is a tiny init)
-    launches = ix.n_tiles
+    # dominant kernel: the tile kernel, one launch per S tile (dense head: per
+    # tiles_per_launch tiles); its average launch duration is the step time over
+    # the launches (the other launches per step are small: output init, query
+    # order, and for the dense head the per-join query preparation)
+    launches = ix.n_tiles if not head else -(-ix.n_tiles // G)
     avg_launch_ms = ms / launches
     bytes_per_launch = walked * entry_bytes / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
-    traffic = _traffic("k_iib_tile/%s/T%d" % (a.workload, ix.tile_width))
-    roof = {"kernel": "k_iib_tile", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+    kname = "k_iibh_tiles" if head else "k_iib_tile"
+    traffic = _traffic("%s/%s/T%d" % (kname, a.workload, ix.tile_width))
+    tail_eps = walked_tail / (ms / 1e3)
+    roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": launches,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             # every walked entry is one local-memory atomic add; gfx950 retires at most one
             # wave64 LDS atomic per 4 clocks per CU (16 lane-ops/clk): 256 CUs x 2.4 GHz x 16
-            "onchip": {"unit": "LDS atomic lane-ops/s", "achieved": eps, "peak": LDS_ATOMIC_PEAK,
-                       "frac": round(eps / LDS_ATOMIC_PEAK, 4)}}
+            "onchip": {"unit": "LDS atomic lane-ops/s", "achieved": tail_eps, "peak": LDS_ATOMIC_PEAK,
+                       "frac": round(tail_eps / LDS_ATOMIC_PEAK, 4)}}
+    if head:
+        # bytes of dense head blocks read per launch (the four queries of a workgroup share each read)
+        hb = -(-n_r // 4) * ix.tile_width * head * min(G, ix.n_tiles)
+        roof["head_block_bytes_per_launch"] = hb
+        roof["head_block_GBps"] = round(hb / (avg_launch_ms / 1e3) / 1e9, 1)
 
     iiib = None
     if not a.no_iiib:
@@ -281,14 +325,17 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8" if sdt == torch.int32 else "f32", "data": "synthetic",
         "config": {"workload": a.workload, "algo": "iib", "schedule": "persistent" if a.persistent else "tile launches",
-                   "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k,
+                   "n_r": n_r, "n_s": n_s, "d": wl["d"], "k": k, "dense_head": head,
+                   "tiles_per_launch": G if head else 1,
                    "tile_width": ix.tile_width, "nnz_s": S.nnz, "nnz_r": R.nnz},
         "postings_entries_per_s": eps, "postings_GBps": round(gbps, 1), "postings_entries_per_step": walked,
+        "walked_entries_per_step": walked_tail, "iib_plain_walk": walk,
         "index_build_s": round(t_build, 3), "oracle_spot_check": {"queries": len(rows), "exact": ok},
         "iiib": iiib, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))
     bad = not ok or (iiib is not None and not all(iiib[v]["identical_to_iib"] for v in ("plain", "refined", "learned")))
+    bad = bad or (walk is not None and not walk["identical_to_dense_head"])
     if bad:
         sys.exit(1)
 

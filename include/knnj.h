@@ -88,7 +88,7 @@ typedef struct {
    * as a dense block per tile; the IIB join then computes their part of every
    * score with byte dot products and walks only the other lists (same exact
    * result; pays off when a few dimensions hold most postings).  0 = off;
-   * otherwise a multiple of 16 in [16, 256]. */
+   * otherwise 64, 128, 192 or 256. */
   int32_t dense_head;
   int32_t reserved[6];
 } knnj_index_opts;
@@ -141,7 +141,10 @@ typedef struct {
    * measures it; without validation 4096 is assumed.  Sizes IIIB's local copy of
    * r when the dimensions are too many for a dense one. */
   int32_t r_max_row_nnz;
-  int32_t reserved[4];
+  /* Dense-head IIB join: S tiles taken by one launch (each workgroup keeps its
+   * queries across them).  0 = default (4). */
+  int32_t tiles_per_launch;
+  int32_t reserved[3];
 } knnj_join_opts;
 
 /*

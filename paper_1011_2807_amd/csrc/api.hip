@@ -30,8 +30,8 @@ knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 knnj_status launch_lpt_order(int64_t n, const int64_t* r_ptr, const int32_t* r_idx, const uint32_t* list_len,
                              uint32_t* bucket, uint32_t* hist, int32_t* order, hipStream_t st);
 knnj_status build_head(Index* ix, hipStream_t st);
-knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids,
-                            void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
+knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t tiles_per_launch,
+                            int32_t* ids, void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
 size_t head_smem_bytes(int tile, int k, int H);
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st);
@@ -68,6 +68,7 @@ static void free_index(Index* ix) {
   (void)hipFree(ix->hj_d);
   (void)hipFree(ix->hj_w);
   (void)hipFree(ix->hj_rh);
+
   (void)hipFree(ix->s_indptr);
   (void)hipFree(ix->s_indices);
   (void)hipFree(ix->s_values);
@@ -128,7 +129,7 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
   const int head = opt ? opt->dense_head : 0;
   if (head != 0) {
     if (S->dtype != KNNJ_U8) return fail(KNNJ_EUNSUPPORTED, "dense_head needs uint8 data");
-    if (head < 16 || head > 256 || (head % 16)) return fail(KNNJ_EINVAL, "dense_head must be a multiple of 16 in [16, 256]");
+    if (head < 64 || head > 256 || (head % 64)) return fail(KNNJ_EINVAL, "dense_head must be 64, 128, 192 or 256");
     if (head_smem_bytes(tile, 1, head) > size_t(max_smem))
       return fail(KNNJ_EUNSUPPORTED, "tile_width too large for the dense-head join's local memory");
   }
@@ -309,6 +310,7 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
   if (o.r_block_rows < 0) return fail(KNNJ_EINVAL, "r_block_rows must be >= 0");
   hipStream_t st = (hipStream_t)stream;
   if (o.r_max_row_nnz < 0 || o.r_max_row_nnz > kMaxRowNnz) return fail(KNNJ_EINVAL, "r_max_row_nnz out of range");
+  if (o.tiles_per_launch < 0) return fail(KNNJ_EINVAL, "tiles_per_launch must be >= 0");
   int32_t max_r = o.r_max_row_nnz > 0 ? o.r_max_row_nnz : kMaxRowNnz;
   if (!(o.flags & KNNJ_FLAG_NO_VALIDATE)) {
     if ((rc = validate_csr(R, ix->dev_err, st, &max_r)) != KNNJ_OK) return rc;
@@ -336,7 +338,7 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
     } else if (ix->head_h > 0 && !(o.flags & KNNJ_FLAG_NO_DENSE_HEAD) &&
                head_smem_bytes(ix->tile, k, ix->head_h) <= size_t(device_max_smem(ix->device))) {
       // (a k too large for the dense-head kernel's local memory takes the plain walk)
-      rc = launch_iib_head(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
+      rc = launch_iib_head(ix, R, k, ix->js_order, o.tiles_per_launch, ids, sc, cnt, slots, st);
     } else {
       rc = launch_iib(ix, R, k, ix->js_order, ids, sc, cnt, slots, st);
     }

@@ -4,22 +4,31 @@
 // data a few dimensions hold most postings, and within an S tile their lists
 // are nearly dense.  For the H dimensions with the longest lists the index also
 // keeps, per tile, the weights as a dense block, and the join computes their
-// part of A[s] = sum_d r[d] * s[d] as byte dot products (v_dot4_u32_u8) instead
-// of one local-memory atomic per posting; only the other ("tail") lists are
-// walked.  Integer sums, so the scores are bit-identical to the plain walk.
+// part of A[s] = sum_d r[d] * s[d] as a dense product instead of one
+// local-memory atomic per posting; only the other ("tail") lists are walked.
+// Integer sums, so the scores are bit-identical to the plain walk.
 //
 // Layout of the block of tile t: [H / 16 chunks][T rows][16 bytes]; byte j of
 // chunk c of row s is the weight of head dimension 16 c + j.  Lanes handling
 // consecutive rows read consecutive 16-byte chunks.
 //
-// The join kernel takes Q = 4 queries per workgroup: each head chunk is loaded
-// once and feeds the dot products of all four queries.
-#include "sched.hpp"
+// A workgroup of the join takes Q queries (the same group for a run of tiles):
+// each head chunk it loads feeds the products of all Q queries, and their tail
+// lists are staged and walked together.  The product runs on the vector units
+// (v_dot4_u32_u8): with Q = 4 query columns it is narrower than the smallest
+// byte matrix-core shape (16 columns), and a wider Q needs more local memory
+// for the score rows than leaves room for enough resident workgroups.
 #include "walk.hpp"
 
 namespace knnj {
 
-constexpr int kHeadQ = 2;
+// defaults: queries per workgroup, S tiles per launch
+constexpr int kHeadQ = 4;
+constexpr int kHeadTiles = 4;
+
+// score rows of the Q queries lie T + kAccPad words apart: the same row slot of
+// different queries falls in different local-memory banks
+constexpr int kAccPad = 4;
 
 // head_pos[d] = rank of d among the H longest lists (ties: smaller d first), or -1.
 // One workgroup; `taken` is a bitmap of n_dims bits in global memory (zeroed).
@@ -51,7 +60,8 @@ __global__ void k_head_select(int32_t n_dims, int32_t H, const uint32_t* __restr
   }
 }
 
-// Scatter the head weights of every S row into the dense blocks (zeroed).
+// Scatter the head weights of every S row into the dense blocks (zeroed).  One
+// wave per row.
 __global__ void k_head_fill(int64_t n_rows, int32_t log2_tile, int32_t H, const int64_t* __restrict__ s_ptr,
                             const int32_t* __restrict__ s_idx, const uint8_t* __restrict__ s_val,
                             const int32_t* __restrict__ head_pos, uint8_t* __restrict__ head) {
@@ -63,8 +73,7 @@ __global__ void k_head_fill(int64_t n_rows, int32_t log2_tile, int32_t H, const 
     const int64_t t = r >> log2_tile, s = r & (T - 1);
     for (int64_t j = s_ptr[r] + lane; j < s_ptr[r + 1]; j += kWave) {
       const int32_t h = head_pos[s_idx[j]];
-      if (h < 0) continue;
-      head[((t * (H / 16) + h / 16) * T + s) * 16 + (h & 15)] = s_val[j];
+      if (h >= 0) head[((t * (H / 16) + h / 16) * T + s) * 16 + (h & 15)] = s_val[j];
     }
   }
 }
@@ -106,73 +115,129 @@ __global__ void k_head_prep(int64_t n_q, int32_t H, const int64_t* __restrict__ 
   if (lane == 0) hj_cnt[q] = n_tail;
 }
 
-// IIB with the dense head for the queries at positions Q b .. Q b + Q - 1 of
-// `order`, on tile t.  Local memory: acc[Q][T] | head weights [Q][H] bytes | stage.
-// The tail lists of the Q queries are staged and walked together (chunks of
-// kSegChunk lists); the first chunk's list lookups are issued before the head
-// dot products, so their latency overlaps that work.
+// Top-k update of the Q queries of a workgroup after one tile (Algorithm 3's
+// candidate step for each of them).  th / cn: the queries' running k-th scores
+// and list sizes, kept in local memory by the workgroup that owns the queries.
+// One pass counts, for every query at once, the scores above its running k-th
+// score, with a single workgroup reduction.  A query with such scores is then
+// merged by one wave (wave i % 4 takes query i) when its list and the new
+// candidates fit in 64 lanes: the candidates are compacted into a per-wave
+// buffer, sorted with the list by a wave-wide bitonic sort on the key (score
+// desc, id asc), and the first k written back.  Larger merges (early tiles with
+// a large k) take the workgroup selection.  red: 4 * Q words, hard: Q words;
+// stage: at least 2 KiB.
 template <int Q>
-__global__ __launch_bounds__(kBlock) void k_iibh_tile(int32_t tile, int32_t log2_tile, int32_t n_dims, int32_t k,
-                                                      int32_t H, int64_t n_q, const int32_t* __restrict__ order,
-                                                      const int64_t* __restrict__ r_ptr,
-                                                      const int32_t* __restrict__ hj_d,
-                                                      const uint8_t* __restrict__ hj_w,
-                                                      const uint32_t* __restrict__ hj_cnt,
-                                                      const uint4* __restrict__ rh_g,
-                                                      const int64_t* __restrict__ offsets, Postings<uint8_t> P,
-                                                      const uint4* __restrict__ head, int32_t* __restrict__ out_ids,
-                                                      uint32_t* __restrict__ out_sc, int32_t* __restrict__ out_cnt,
-                                                      uint64_t* __restrict__ slots) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ uint32_t tmp[kBlock / kWave + 1];
-  const int T = 1 << log2_tile;
-  uint32_t* acc = reinterpret_cast<uint32_t*>(smem);                    // [Q][T]
-  uint4* rh = reinterpret_cast<uint4*>(smem + size_t(Q) * T * 4);       // [Q][H / 16]
-  char* stage = smem + size_t(Q) * T * 4 + size_t(Q) * H;
-  const int64_t s_base = int64_t(tile) << log2_tile;
-  const int64_t key0 = int64_t(tile) * n_dims;
-  const int HC = H / 16;
-  int64_t qs[Q], tb[Q];
-  uint32_t pre[Q + 1];
-  pre[0] = 0;
+__device__ __forceinline__ void group_select(const uint32_t* acc, int stride, int T, int64_t s_base, int k,
+                                             const int64_t* qs, int32_t* __restrict__ out_ids,
+                                             uint32_t* __restrict__ out_sc, int32_t* __restrict__ out_cnt,
+                                             char* stage, uint32_t* tmp, uint32_t* red, uint32_t* hard, uint32_t* th,
+                                             int32_t* cn) {
+  uint32_t c[Q], thv[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const int64_t p = int64_t(blockIdx.x) * Q + i;
-    qs[i] = p < n_q ? (order ? int64_t(order[p]) : p) : -1;
-    tb[i] = qs[i] >= 0 ? r_ptr[qs[i]] : 0;
-    pre[i + 1] = pre[i] + (qs[i] >= 0 ? hj_cnt[qs[i]] : 0u);
+    c[i] = 0u;
+    thv[i] = th[i];
   }
-  const uint32_t n_tail = pre[Q];
-  // list lookup of tail list g (< n_tail) of the group
-  auto lookup = [&](uint32_t g, int64_t* beg, uint32_t* len, uint32_t* w) {
-    int i = 0;
+  for (int x = threadIdx.x; x < T; x += kBlock) {
 #pragma unroll
-    for (int x = 1; x < Q; ++x) i += g >= pre[x];
-    const int64_t at = tb[i] + (g - pre[i]);
-    const int64_t key = key0 + hj_d[at];
-    *beg = offsets[key];
-    *len = uint32_t(offsets[key + 1] - *beg);
-    *w = (uint32_t(i) << 8) | hj_w[at];
-  };
-  int64_t beg = 0;
-  uint32_t len = 0, w = 0;
-  if (threadIdx.x < n_tail) lookup(threadIdx.x, &beg, &len, &w);
-  for (int x = threadIdx.x; x < Q * HC; x += kBlock) {
-    const int i = x / HC;
-    rh[x] = qs[i] >= 0 ? rh_g[qs[i] * HC + (x - i * HC)] : make_uint4(0u, 0u, 0u, 0u);
+    for (int i = 0; i < Q; ++i) c[i] += acc[i * stride + x] > thv[i] ? 1u : 0u;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) c[i] += __shfl_xor(c[i], o, kWave);
+    if (lane == 0) red[wv * Q + i] = c[i];
   }
   __syncthreads();
-  // head part: a thread takes rows s0 + 256 j (j < RB) at a time; each 16-byte
-  // chunk of a row feeds the dot products of all Q queries, and each chunk of
-  // the queries' weights (one local-memory broadcast) feeds RB rows
+  uint64_t* kb = reinterpret_cast<uint64_t*>(stage) + wv * kWave;
+  const uint64_t below = (uint64_t(1) << lane) - 1u;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if ((i & 3) != wv) continue;
+    uint32_t n = 0;
+#pragma unroll
+    for (int x = 0; x < kBlock / kWave; ++x) n += red[x * Q + i];
+    const int cnt = cn[i];
+    const bool big = n > 0 && qs[i] >= 0 && n + uint32_t(cnt) > uint32_t(kWave);
+    if (lane == 0) hard[i] = big ? 1u : 0u;
+    if (n == 0 || qs[i] < 0 || big) continue;
+    const int64_t q = qs[i];
+    int32_t* o_ids = out_ids + q * k;
+    uint32_t* o_sc = out_sc + q * k;
+    const uint32_t* a = acc + size_t(i) * stride;
+    // the list, then the candidates in slot order
+    if (lane < cnt) kb[lane] = (uint64_t(o_sc[lane]) << 32) | uint32_t(~uint32_t(o_ids[lane]));
+    uint32_t m = uint32_t(cnt);
+    for (int x0 = 0; x0 < T; x0 += kWave) {
+      const uint32_t v = a[x0 + lane];
+      const bool take = v > thv[i];
+      const uint64_t bal = __ballot(take);
+      if (take)
+        kb[m + __popcll(bal & below)] =
+            (uint64_t(v) << 32) | uint32_t(~uint32_t(s_base + swz(uint32_t(x0 + lane))));
+      m += uint32_t(__popcll(bal));
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint64_t key = uint64_t(lane) < m ? kb[lane] : 0ull;
+    // bitonic sort of the 64 lanes' keys, descending
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+      for (int st = size >> 1; st > 0; st >>= 1) {
+        const uint32_t lo = __shfl_xor(uint32_t(key), st, kWave);
+        const uint32_t hi = __shfl_xor(uint32_t(key >> 32), st, kWave);
+        const uint64_t other = (uint64_t(hi) << 32) | lo;
+        const bool desc = (lane & size) == 0 || size == kWave;
+        const bool lower = (lane & st) == 0;
+        const uint64_t mx = key > other ? key : other, mn = key > other ? other : key;
+        key = lower == desc ? mx : mn;
+      }
+    }
+    const int keep = int(m) < k ? int(m) : k;
+    if (lane < keep) {
+      o_ids[lane] = int32_t(~uint32_t(key));
+      o_sc[lane] = uint32_t(key >> 32);
+    }
+    if (lane == 0) {
+      out_cnt[q] = keep;
+      cn[i] = keep;
+    }
+    if (keep == k && lane == k - 1) th[i] = uint32_t(key >> 32);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (!hard[i]) continue;
+    const int64_t q = qs[i];
+    const SelectSmem sm = select_smem(stage, k, tmp);
+    tile_select<uint32_t, true>(acc + size_t(i) * stride, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q,
+                                sm);
+    // the merged list is still in local memory: m = sm.scal[2] keys, sorted
+    if (threadIdx.x == 0) {
+      const int m = int(sm.scal[2]);
+      const int keep = m < k ? m : k;
+      cn[i] = keep;
+      th[i] = keep == k ? uint32_t(sm.keys[k - 1] >> 32) : 0u;
+    }
+    __syncthreads();
+  }
+}
+
+// Head part of one tile on the vector units: thread rows s0 + 256 j (j < RB);
+// each 16-byte chunk of a row feeds the byte dot products (v_dot4_u32_u8) of
+// all Q queries, and each chunk of the queries' weights (one local-memory
+// broadcast) feeds RB rows.
+template <int Q, int HC>
+__device__ __forceinline__ void head_dot4(uint32_t* acc, int stride, int T, const uint4* blk, const uint4* rh) {
   constexpr int RB = 4;
-  const uint4* blk = head + size_t(tile) * HC * T;
   for (int s0 = threadIdx.x; s0 < T; s0 += RB * kBlock) {
     uint32_t a[Q][RB];
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
       for (int j = 0; j < RB; ++j) a[i][j] = 0u;
+#pragma unroll 1
     for (int c = 0; c < HC; ++c) {
       uint4 v[RB];
 #pragma unroll
@@ -197,41 +262,137 @@ __global__ __launch_bounds__(kBlock) void k_iibh_tile(int32_t tile, int32_t log2
       const int s = s0 + j * kBlock;
       if (s < T) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) acc[i * T + swz(uint32_t(s))] = a[i][j];
+        for (int i = 0; i < Q; ++i) acc[i * stride + swz(uint32_t(s))] = a[i][j];
       }
     }
   }
-  // tail lists of all Q queries (stage_write's scan orders the head stores
-  // before the walk's atomics)
-  uint64_t walked = 0;
-  for (uint32_t c0 = 0; c0 < n_tail; c0 += kSegChunk) {
-    const int n = int(n_tail - c0 < uint32_t(kSegChunk) ? n_tail - c0 : uint32_t(kSegChunk));
-    if (c0 > 0) {
-      beg = 0;
-      len = 0;
-      w = 0;
-      if (threadIdx.x < n) lookup(c0 + threadIdx.x, &beg, &len, &w);
+}
+
+// Per-workgroup state of the join kept in local memory for the whole launch
+// (registers stay free for the walk and the selection).
+template <int Q>
+struct GroupState {
+  int64_t qs[Q];        // query ids (-1: none)
+  int64_t tb[Q];        // first CSR position of each query
+  uint32_t pre[Q + 1];  // prefix of the queries' tail-feature counts
+  uint32_t th[Q];       // running k-th score (0 until k are held)
+  int32_t cn[Q];        // running list size
+  uint32_t red[4 * Q];  // selection scratch
+  uint32_t hard[Q];
+};
+
+// IIB with the dense head for the queries at positions Q b .. Q b + Q - 1 of
+// `order`, on tiles t0 .. t1 - 1 in ascending order (each tile is one step of
+// Algorithm 1's inner loop for these queries).  Local memory: acc[Q][T +
+// kAccPad] | head weights [Q][H] bytes | stage.  What does not depend on the
+// tile (the queries, their tail features, their head weights, their running
+// k-th scores) is loaded once; the list bounds of the next tile are loaded
+// while the current tile is processed.
+template <int Q, int HK>
+__global__ __launch_bounds__(kBlock) void k_iibh_tiles(int32_t t0, int32_t t1, int32_t log2_tile, int32_t n_dims,
+                                                       int32_t k, int64_t n_q, const int32_t* __restrict__ order,
+                                                       const int64_t* __restrict__ r_ptr,
+                                                       const int32_t* __restrict__ hj_d,
+                                                       const uint8_t* __restrict__ hj_w,
+                                                       const uint32_t* __restrict__ hj_cnt,
+                                                       const uint4* __restrict__ rh_g,
+                                                       const int64_t* __restrict__ offsets, Postings<uint8_t> P,
+                                                       const uint4* __restrict__ head, int32_t* __restrict__ out_ids, uint32_t* __restrict__ out_sc,
+                                                       int32_t* __restrict__ out_cnt, uint64_t* __restrict__ slots) {
+  constexpr int H = 64 * HK, HC = 4 * HK;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ uint32_t tmp[kBlock / kWave + 1];
+  __shared__ GroupState<Q> gs;
+  const int T = 1 << log2_tile;
+  const int stride = T + kAccPad;
+  uint32_t* acc = reinterpret_cast<uint32_t*>(smem);                        // [Q][stride]
+  uint4* rh = reinterpret_cast<uint4*>(smem + size_t(Q) * stride * 4);      // [Q][HC]
+  char* stage = smem + size_t(Q) * stride * 4 + size_t(Q) * H;
+  if (threadIdx.x == 0) {
+    gs.pre[0] = 0;
+    for (int i = 0; i < Q; ++i) {
+      const int64_t p = int64_t(blockIdx.x) * Q + i;
+      const int64_t q = p < n_q ? (order ? int64_t(order[p]) : p) : -1;
+      gs.qs[i] = q;
+      gs.tb[i] = q >= 0 ? r_ptr[q] : 0;
+      gs.pre[i + 1] = gs.pre[i] + (q >= 0 ? hj_cnt[q] : 0u);
+      const int32_t c = q >= 0 ? out_cnt[q] : 0;
+      gs.cn[i] = c;
+      gs.th[i] = c == k ? out_sc[q * k + k - 1] : 0u;
     }
-    const uint32_t total = stage_write<uint32_t>(stage, tmp, n, beg, len, w);
-    walk_lists<uint8_t, uint32_t, true>(acc, stage, n, total, P, log2_tile);
-    if (slots) walked += block_sum(threadIdx.x < n ? len : 0u, tmp);
-    __syncthreads();
   }
-  if (n_tail == 0) __syncthreads();
-  for (int i = 0; i < Q; ++i) {
-    if (qs[i] < 0) continue;
-    const int64_t q = qs[i];
-    tile_select<uint32_t, true>(acc + size_t(i) * T, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q,
-                                select_smem(stage, k, tmp));
+  __syncthreads();
+  const uint32_t n_tail = gs.pre[Q];
+  // tail list g (< n_tail) of the group: dimension and (slot << 8) | weight
+  auto tail_list = [&](uint32_t g, int32_t* d, uint32_t* w) {
+    int i = 0;
+#pragma unroll
+    for (int x = 1; x < Q; ++x) i += g >= gs.pre[x];
+    const int64_t at = gs.tb[i] + (g - gs.pre[i]);
+    *d = hj_d[at];
+    *w = (uint32_t(i) << 8) | hj_w[at];
+  };
+  // the first kSegChunk tail lists stay in registers for all tiles
+  int32_t d0 = 0;
+  uint32_t w0 = 0;
+  if (threadIdx.x < n_tail) tail_list(threadIdx.x, &d0, &w0);
+  for (int x = threadIdx.x; x < Q * HC; x += kBlock) {
+    const int i = x / HC;
+    const int64_t q = gs.qs[i];
+    rh[x] = q >= 0 ? rh_g[q * HC + (x - i * HC)] : make_uint4(0u, 0u, 0u, 0u);
+  }
+  int64_t nb = 0, ne = 0;  // bounds of list (tile, d0)
+  if (threadIdx.x < n_tail) {
+    nb = offsets[int64_t(t0) * n_dims + d0];
+    ne = offsets[int64_t(t0) * n_dims + d0 + 1];
+  }
+  uint64_t walked = 0;
+  for (int32_t tile = t0; tile < t1; ++tile) {
+    const int64_t s_base = int64_t(tile) << log2_tile;
+    const int64_t key0 = int64_t(tile) * n_dims;
+    const int64_t beg = nb;
+    const uint32_t len = uint32_t(ne - nb);
+    if (tile + 1 < t1 && threadIdx.x < n_tail) {
+      nb = offsets[key0 + n_dims + d0];
+      ne = offsets[key0 + n_dims + d0 + 1];
+    }
+    __syncthreads();  // rh is in place; the previous tile's selection is done with acc and stage
+    const uint4* blk = head + size_t(tile) * HC * T;
+    head_dot4<Q, HC>(acc, stride, T, blk, rh);
+    // tail lists of all Q queries (stage_write's scan orders the head stores
+    // before the walk's atomics)
+    for (uint32_t c0 = 0; c0 < n_tail; c0 += kSegChunk) {
+      const int n = int(n_tail - c0 < uint32_t(kSegChunk) ? n_tail - c0 : uint32_t(kSegChunk));
+      int64_t b = beg;
+      uint32_t l = len, w = w0;
+      if (c0 > 0) {
+        b = 0;
+        l = 0;
+        w = 0;
+        if (threadIdx.x < n) {
+          int32_t d;
+          tail_list(c0 + threadIdx.x, &d, &w);
+          b = offsets[key0 + d];
+          l = uint32_t(offsets[key0 + d + 1] - b);
+        }
+      } else if (threadIdx.x >= n) {
+        l = 0;
+      }
+      const uint32_t total = stage_write<uint32_t>(stage, tmp, n, b, l, w);
+      walk_lists<uint8_t, uint32_t, true>(acc, stage, n, total, P, stride);
+      if (slots) walked += block_sum(threadIdx.x < n ? l : 0u, tmp);
+      __syncthreads();
+    }
+    if (n_tail == 0) __syncthreads();
+    group_select<Q>(acc, stride, T, s_base, k, gs.qs, out_ids, out_sc, out_cnt, stage, tmp, gs.red, gs.hard, gs.th,
+                    gs.cn);
   }
   if (threadIdx.x == 0 && slots)
     atomicAdd((unsigned long long*)&slots[KNNJ_STAT_POSTINGS * 256 + (blockIdx.x & 255)], (unsigned long long)walked);
 }
 
-size_t tile_smem_bytes(int tile, int k);
-
 size_t head_smem_bytes(int tile, int k, int H) {
-  return size_t(kHeadQ) * tile * 4 + size_t(kHeadQ) * H + stage_bytes(k);
+  return size_t(kHeadQ) * (tile + kAccPad) * 4 + size_t(kHeadQ) * H + stage_bytes(k);
 }
 
 knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
@@ -286,8 +447,8 @@ static knnj_status ensure_head_scratch(Index* ix, int64_t n, int64_t nnz) {
   return KNNJ_OK;
 }
 
-knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids,
-                            void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st) {
+knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t tiles_per_launch,
+                            int32_t* ids, void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st) {
   const int64_t n = R->n_rows;
   if (n == 0) return KNNJ_OK;
   const int H = ix->head_h;
@@ -297,13 +458,24 @@ knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32
   k_head_prep<<<unsigned((n + 3) / 4), kBlock, 0, st>>>(n, H, R->indptr, R->indices, (const uint8_t*)R->values,
                                                        ix->head_pos, ix->hj_d, ix->hj_w, ix->hj_cnt, ix->hj_rh);
   const size_t smem = head_smem_bytes(ix->tile, k, H);
-  const unsigned g = unsigned((n + kHeadQ - 1) / kHeadQ);
   Postings<uint8_t> P{reinterpret_cast<const uint4*>(ix->post_u8)};
-  for (int32_t t = 0; t < ix->n_tiles; ++t)
-    k_iibh_tile<kHeadQ><<<g, kBlock, smem, st>>>(t, ix->log2_tile, ix->n_dims, k, H, n, order, R->indptr, ix->hj_d,
-                                                 ix->hj_w, ix->hj_cnt, reinterpret_cast<const uint4*>(ix->hj_rh),
-                                                 ix->offsets, P, reinterpret_cast<const uint4*>(ix->head_blk), ids,
-                                                 (uint32_t*)sc, cnt, slots);
+  const unsigned g = unsigned((n + kHeadQ - 1) / kHeadQ);
+  const int32_t G = tiles_per_launch > 0 ? tiles_per_launch : kHeadTiles;
+  for (int32_t t = 0; t < ix->n_tiles; t += G) {
+    const int32_t t1 = t + G < ix->n_tiles ? t + G : ix->n_tiles;
+#define KNNJ_IIBH(HK)                                                                                              \
+  k_iibh_tiles<kHeadQ, HK><<<g, kBlock, smem, st>>>(                                                               \
+      t, t1, ix->log2_tile, ix->n_dims, k, n, order, R->indptr, ix->hj_d, ix->hj_w, ix->hj_cnt,                    \
+      reinterpret_cast<const uint4*>(ix->hj_rh), ix->offsets, P, reinterpret_cast<const uint4*>(ix->head_blk), ids, \
+      (uint32_t*)sc, cnt, slots);
+    switch (H / 64) {
+      case 1: KNNJ_IIBH(1) break;
+      case 2: KNNJ_IIBH(2) break;
+      case 3: KNNJ_IIBH(3) break;
+      default: KNNJ_IIBH(4) break;
+    }
+#undef KNNJ_IIBH
+  }
   KNNJ_HIP(hipGetLastError());
   return KNNJ_OK;
 }

@@ -95,11 +95,11 @@ __device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int6
 // list's range are added into acc (swizzled slots) with local-memory atomics.
 // A lane only steps over the lists inside its team's range.
 // kMulti (uint8 only): the lists belong to several queries; a list's weight
-// word is (slot << 8) | w and its scores go to acc + (slot << log2_tile).
+// word is (slot << 8) | w and its scores go to acc + slot * acc_stride.
 constexpr int kTeam = 8;
 template <typename V, typename S, bool kMulti = false>
 __device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P,
-                                           int log2_tile = 0) {
+                                           int acc_stride = 0) {
   constexpr int U = 4;
   const uint32_t* pre = reinterpret_cast<const uint32_t*>(stage + kPreOff);
   const int64_t* cbase = reinterpret_cast<const int64_t*>(stage + kCbOff);
@@ -161,7 +161,7 @@ __device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_list
       if constexpr (sizeof(V) == 1) {
         const uint32_t x[4] = {e[u].x, e[u].y, e[u].z, e[u].w};
         if constexpr (kMulti) {
-          S* a = acc + (size_t(ww[u] >> 8) << log2_tile);
+          S* a = acc + size_t(ww[u] >> 8) * acc_stride;
           const uint32_t wq = ww[u] & 0xffu;
 #pragma unroll
           for (int i = 0; i < 4; ++i)

@@ -47,7 +47,8 @@ class _IndexOpts(ctypes.Structure):
 class _JoinOpts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("flags", ctypes.c_uint32), ("r_block_rows", ctypes.c_int64),
                 ("theta_seed", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("fallback_out", ctypes.c_void_p),
-                ("level_drop", ctypes.c_int32), ("r_max_row_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("level_drop", ctypes.c_int32), ("r_max_row_nnz", ctypes.c_int32),
+                ("tiles_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class _IndexInfo(ctypes.Structure):
@@ -181,8 +182,8 @@ class Index:
 
 
 def build_index(S: DeviceCSR, tile_width: int = 0, dense_head: int = 0, stream=None) -> Index:
-    """dense_head: uint8 data only; keep that many longest-list dimensions as dense
-    per-tile blocks for the IIB join (0 = off)."""
+    """dense_head: uint8 data only; keep that many (64, 128, 192 or 256)
+    longest-list dimensions as dense per-tile blocks for the IIB join (0 = off)."""
     lib = load_library()
     h = ctypes.c_void_p()
     opts = _IndexOpts(int(tile_width), int(dense_head))
@@ -203,7 +204,7 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
              theta_seed: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
              fallback_out: Optional[torch.Tensor] = None, validate: bool = True, bound_filter: bool = False,
              level_drop: int = 0, persistent: bool = False, r_max_row_nnz: int = 0, dense_head: bool = True,
-             out=None, stream=None):
+             tiles_per_launch: int = 0, out=None, stream=None):
     """Exact top-k of every row of R against the indexed S.
 
     Returns (ids int32[n,k], scores int32|float32[n,k], count int32[n]) on the device.
@@ -213,6 +214,7 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     bound_filter / level_drop: IIIB refinements (see knnj.h); results stay exact.
     persistent: one persistent launch per S tile with a device work queue (IIB).
     dense_head: use the index's dense head if it has one (IIB); False walks every list.
+    tiles_per_launch: S tiles per launch of the dense-head join (0 = default).
     """
     lib = load_library()
     ids, sc, cnt = _outputs(R.n_rows, k, index.dtype, out)
@@ -223,6 +225,7 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     o.level_drop = int(level_drop)
     o.r_max_row_nnz = int(r_max_row_nnz)
     o.r_block_rows = int(r_block_rows)
+    o.tiles_per_launch = int(tiles_per_launch)
     if theta_seed is not None:
         assert theta_seed.dtype == torch.float32 and theta_seed.is_cuda and theta_seed.numel() == R.n_rows
     if stats is not None:

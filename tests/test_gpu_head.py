@@ -39,8 +39,9 @@ def zipf():
     return S, R, oracle.bf_topk(R, S, 10)
 
 
-@pytest.mark.parametrize("tile,head,k", [(4096, 64, 10), (2048, 128, 10), (1024, 16, 1), (4096, 256, 100),
-                                         (256, 32, 10)])
+@pytest.mark.parametrize("tile,head,k", [(4096, 64, 10), (2048, 128, 10), (1024, 64, 1), (4096, 256, 100),
+                                         (256, 64, 10), (1024, 128, 10), (1024, 192, 5), (512, 256, 1),
+                                         (2048, 128, 60), (8192, 128, 10)])
 def test_zipf_head_bit_exact(zipf, tile, head, k):
     S, R, want10 = zipf
     want = want10 if k == 10 else oracle.bf_topk(R, S, k)
@@ -66,7 +67,7 @@ def test_tiny_head_bit_exact():
     S = synth.make("tiny", "S")
     R = synth.make("tiny", "R")
     want = oracle.bf_topk(R, S, 10)
-    for tile, head in ((1024, 16), (4096, 48)):
+    for tile, head in ((1024, 64), (4096, 192), (2048, 256)):
         ix = kj.build_index(_dev(S), tile_width=tile, dense_head=head)
         got = kj.knn_join(ix, _dev(R), 10)
         torch.cuda.synchronize()
@@ -86,7 +87,7 @@ def test_head_edge_cases():
         R = _csr(queries[:n_q], 12)
         for k in (1, 5, 1024):
             want = oracle.bf_topk(R, S, k)
-            for tile, head in ((256, 16), (512, 32)):
+            for tile, head in ((256, 64), (512, 128)):
                 ix = kj.build_index(_dev(S), tile_width=tile, dense_head=head)
                 got = kj.knn_join(ix, _dev(R), k)
                 torch.cuda.synchronize()
@@ -106,6 +107,6 @@ def test_head_rejections():
     with pytest.raises(kj.KnnjError):
         kj.build_index(_dev(f), dense_head=64)
     u = synth.draw(12, 500, 300, (5, 20), features="uniform")
-    for bad in (8, 20, 272, -16):
+    for bad in (8, 16, 96, 320, -64):
         with pytest.raises(kj.KnnjError):
             kj.build_index(_dev(u), dense_head=bad)
