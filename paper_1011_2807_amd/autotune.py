@@ -4,6 +4,8 @@ Times candidate settings on the device (HIP events around real joins of a
 query sample) and keeps the fastest:
 
 * tile width T (rows of S per tile: the LDS score array and the list split),
+* for IIB on uint8 data, the dense head (0 = plain walk, or the number of
+  longest-list dimensions kept as dense per-tile blocks),
 * schedule (one launch per tile, or the persistent work-queue launch),
 * for IIIB, the level drop of the refined variant.
 
@@ -24,6 +26,7 @@ import torch
 from . import knnj as kj
 
 DEFAULT_TILES = (2048, 4096, 8192)
+CACHE_VERSION = 2  # bumped when the candidate set changes
 
 
 def _cache_path() -> str:
@@ -56,8 +59,9 @@ def signature(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str) -> str
     nnz_s = int(S.indices.shape[0])
     nnz_r = int(R_sample.indices.shape[0])
     mean_r = nnz_r / max(1, R_sample.n_rows)
-    return "%s|S%d|nnz%d|D%d|%s|k%d|%s|r%.0f" % (_arch(), S.n_rows, int(math.log2(max(1, nnz_s))), S.n_dims,
-                                                 "u8" if S.dtype == kj.KNNJ_U8 else "f32", k, algo, mean_r)
+    return "v%d|%s|S%d|nnz%d|D%d|%s|k%d|%s|r%.0f" % (CACHE_VERSION, _arch(), S.n_rows, int(math.log2(max(1, nnz_s))),
+                                                     S.n_dims, "u8" if S.dtype == kj.KNNJ_U8 else "f32", k, algo,
+                                                     mean_r)
 
 
 def _time(fn, reps: int = 2) -> float:
@@ -74,12 +78,13 @@ def _time(fn, reps: int = 2) -> float:
 
 
 def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", tiles: Iterable[int] = DEFAULT_TILES,
-         drops: Iterable[int] = (0, 2, 4, 6), use_cache: bool = True, verbose: bool = False) -> Dict:
+         drops: Iterable[int] = (0, 2, 4, 6), heads: Iterable[int] = (0, 128, 192), use_cache: bool = True,
+         verbose: bool = False) -> Dict:
     """Fastest settings for joining queries like R_sample against S.
 
-    Returns {"tile_width", "persistent", "level_drop", "ms", "timings"}; the index
-    must then be built with tile_width.  R_sample should hold a few thousand
-    queries drawn like the real ones.
+    Returns {"tile_width", "dense_head", "persistent", "level_drop", "ms",
+    "timings"}; the index must then be built with tile_width and dense_head.
+    R_sample should hold a few thousand queries drawn like the real ones.
     """
     key = signature(S, R_sample, k, algo)
     tab = _load_cache() if use_cache else {}
@@ -91,31 +96,35 @@ def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", til
            torch.empty((R_sample.n_rows, k), dtype=torch.int32 if S.dtype == kj.KNNJ_U8 else torch.float32,
                        device="cuda"),
            torch.empty(R_sample.n_rows, dtype=torch.int32, device="cuda"))
+    hs = tuple(heads) if (algo == "iib" and S.dtype == kj.KNNJ_U8) else (0,)
     for t in tiles:
-        try:
-            ix = kj.build_index(S, tile_width=t)
-        except kj.KnnjError:
-            continue
-        cands = []
-        if algo == "iib":
-            cands = [dict(persistent=False), dict(persistent=True)]
-        else:
-            cands = [dict(bound_filter=True, level_drop=d) for d in drops]
-        for c in cands:
+        for h in hs:
             try:
-                ms = _time(lambda: kj.knn_join(ix, R_sample, k, algo=algo, validate=False, out=out, **c))
+                ix = kj.build_index(S, tile_width=t, dense_head=h)
             except kj.KnnjError:
                 continue
-            rec = {"tile_width": t, "ms": round(ms, 3), **c}
-            timings.append(rec)
-            if verbose:
-                print("autotune", rec, flush=True)
-            if best is None or ms < best["ms"]:
-                best = rec
-        ix.free()
+            if algo == "iiib":
+                cands = [dict(bound_filter=True, level_drop=d) for d in drops]
+            elif h:
+                cands = [dict()]
+            else:
+                cands = [dict(persistent=False), dict(persistent=True)]
+            for c in cands:
+                try:
+                    ms = _time(lambda: kj.knn_join(ix, R_sample, k, algo=algo, validate=False, out=out, **c))
+                except kj.KnnjError:
+                    continue
+                rec = {"tile_width": t, "dense_head": h, "ms": round(ms, 3), **c}
+                timings.append(rec)
+                if verbose:
+                    print("autotune", rec, flush=True)
+                if best is None or ms < best["ms"]:
+                    best = rec
+            ix.free()
     if best is None:
         raise RuntimeError("autotune: no candidate ran")
-    res = {"tile_width": best["tile_width"], "persistent": bool(best.get("persistent", False)),
+    res = {"tile_width": best["tile_width"], "dense_head": int(best.get("dense_head", 0)),
+           "persistent": bool(best.get("persistent", False)),
            "level_drop": int(best.get("level_drop", 0)), "bound_filter": bool(best.get("bound_filter", False)),
            "ms": best["ms"], "timings": timings, "signature": key}
     if use_cache:
