@@ -121,12 +121,6 @@ def main():
     if a.workload == "batched":
         return run_batched(a)
     wl = synth.WORKLOADS[a.workload]
-    if a.workload == "fp32" and (a.n_s or wl["n_s"]) > 1_000_000:
-        # a run at the full size of this workload (10M vectors, 100K dimensions) made a
-        # device memory fault whose cause is not found yet; smaller S only
-        print("bench.py: the fp32 workload runs with --n-s <= 1,000,000 until its full-size fault is explained",
-              file=sys.stderr)
-        sys.exit(2)
     k = a.k or wl["k"][-1]
     n_r = a.n_r or wl["n_r"]
     n_s = a.n_s or wl["n_s"]
@@ -157,6 +151,7 @@ def main():
     head = a.dense_head if a.dense_head >= 0 else (128 if S.values.dtype == np.uint8 else 0)
     if a.persistent:
         head = 0
+    _log("building the index")
     tb = time.time()
     ix = kj.build_index(dS, tile_width=a.tile or (2048 if head else 0), dense_head=head)
     torch.cuda.synchronize()
@@ -270,8 +265,11 @@ def main():
             return res
 
         # allocate the index-level IIIB buffers outside the timed legs
+        _log("first IIIB join (IIIB buffers)")
         one = kj.DeviceCSR(dR.indptr[:2].contiguous(), dR.indices, dR.values, dR.n_dims)
         kj.knn_join(ix, one, k, algo="iiib", validate=False)
+        torch.cuda.synchronize()
+        _log("first IIIB join done")
         iiib["plain"] = timed_join("iiib plain")
         iiib["refined"] = timed_join("iiib refined", bound_filter=True, level_drop=4)
         # learned seed: labels are the exact k-th scores of the training queries

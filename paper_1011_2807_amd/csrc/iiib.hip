@@ -278,17 +278,19 @@ __global__ void k_sort_buckets(const int64_t* __restrict__ offsets, const int64_
   }
 }
 
+// grid-stride (capped grid: a dispatch counts its work-items in 32 bits)
 __global__ void k_finalize_iiib_u8(const uint64_t* __restrict__ rec, int64_t n, uint32_t* __restrict__ post) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) post[i] = uint32_t(rec[i]);
+  const int64_t step = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) post[i] = uint32_t(rec[i]);
 }
 __global__ void k_finalize_iiib_f32(const uint64_t* __restrict__ rec, int64_t n, uint16_t* __restrict__ ps,
                                     float* __restrict__ pw) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t x = rec[i];
-  ps[i] = uint16_t((x >> 32) & 0xffffu);
-  pw[i] = __uint_as_float(uint32_t(x));
+  const int64_t step = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
+    const uint64_t x = rec[i];
+    ps[i] = uint16_t((x >> 32) & 0xffffu);
+    pw[i] = __uint_as_float(uint32_t(x));
+  }
 }
 
 // ---------------------------------------------------------------- join
@@ -581,7 +583,8 @@ static knnj_status build_block(Index* ix, const knnj_csr* R, int64_t r0, int64_t
     k_sort_buckets<<<kSortGrid, kBlock, kBucketSlots * sizeof(uint32_t), st>>>(
         ix->offsets, ix->iiib_big, n_big, ix->iiib_cut, ix->rec_tmp, ix->iiib_out_tmp, ix->tile);
     if (ix->nnz > 0) {
-      const unsigned gf = unsigned((ix->nnz + kBlock - 1) / kBlock);
+      const int64_t nbf = (ix->nnz + kBlock - 1) / kBlock;
+      const unsigned gf = unsigned(nbf < (int64_t(1) << 20) ? nbf : (int64_t(1) << 20));
       if (ix->dtype == KNNJ_U8) k_finalize_iiib_u8<<<gf, kBlock, 0, st>>>(ix->rec_tmp, ix->nnz, ix->iiib_post);
       else k_finalize_iiib_f32<<<gf, kBlock, 0, st>>>(ix->rec_tmp, ix->nnz, ix->iiib_post_s, ix->iiib_post_w);
     }

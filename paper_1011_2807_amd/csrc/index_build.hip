@@ -268,20 +268,23 @@ __global__ void k_sort_large(const int64_t* __restrict__ offsets, const int64_t*
 }
 
 // ---------------------------------------------------------------- finalize
+// grid-stride (capped grid: a dispatch counts its work-items in 32 bits)
 __global__ void k_finalize_u8(const uint64_t* __restrict__ rec, int64_t n, uint32_t* __restrict__ post) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t x = rec[i];
-  post[i] = (uint32_t(x >> 32) << 16) | ((uint32_t(x) & 0xffu) << 8);
+  const int64_t step = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
+    const uint64_t x = rec[i];
+    post[i] = (uint32_t(x >> 32) << 16) | ((uint32_t(x) & 0xffu) << 8);
+  }
 }
 
 __global__ void k_finalize_f32(const uint64_t* __restrict__ rec, int64_t n, uint16_t* __restrict__ ps,
                                float* __restrict__ pw) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t x = rec[i];
-  ps[i] = uint16_t(x >> 32);
-  pw[i] = __uint_as_float(uint32_t(x));
+  const int64_t step = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
+    const uint64_t x = rec[i];
+    ps[i] = uint16_t(x >> 32);
+    pw[i] = __uint_as_float(uint32_t(x));
+  }
 }
 
 __global__ void k_list_lengths(const uint32_t* __restrict__ cnt, int32_t n_dims, int32_t n_tiles,
@@ -397,7 +400,7 @@ knnj_status build_postings(Index* ix, const int64_t* indptr, const int32_t* indi
                                                                          ix->tile);
     }
     if (ix->nnz > 0) {
-      const unsigned gf = unsigned((ix->nnz + kBlock - 1) / kBlock);
+      const unsigned gf = grid_for(ix->nnz, kBlock);
       if (ix->dtype == KNNJ_U8) k_finalize_u8<<<gf, kBlock, 0, st>>>(ix->rec_tmp, ix->nnz, ix->post_u8);
       else k_finalize_f32<<<gf, kBlock, 0, st>>>(ix->rec_tmp, ix->nnz, ix->post_s, ix->post_w);
     }

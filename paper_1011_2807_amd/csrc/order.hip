@@ -9,9 +9,12 @@ namespace knnj {
 
 constexpr int kCostBuckets = 64;
 
+// Grid-stride fill: a dispatch counts its work-items in 32 bits, so the grid is
+// capped and each thread covers every (grid size)-th word (the IIIB cut table
+// alone exceeds 2^32 words at 10M rows x 100K dimensions).
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  const int64_t step = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) p[i] = v;
 }
 
 __device__ __forceinline__ uint32_t cost_bucket(uint64_t c) {
@@ -55,7 +58,9 @@ __global__ void k_cost_scatter(int64_t n, const uint32_t* __restrict__ bucket, u
 }
 
 knnj_status launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
-  if (n > 0) k_fill_u32<<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(p, n, v);
+  constexpr int64_t kMaxFillBlocks = int64_t(1) << 20;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  if (n > 0) k_fill_u32<<<unsigned(nb < kMaxFillBlocks ? nb : kMaxFillBlocks), kBlock, 0, st>>>(p, n, v);
   KNNJ_HIP(hipGetLastError());
   return KNNJ_OK;
 }
