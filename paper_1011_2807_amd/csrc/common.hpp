@@ -106,6 +106,12 @@ struct ScoreOf<float> {
 __device__ __forceinline__ uint32_t score_bits(uint32_t v) { return v; }
 __device__ __forceinline__ uint32_t score_bits(float v) { return __float_as_uint(v); }
 
+// Slot of row s_local in a swizzled score array: the low five address bits are
+// XORed with the next five, so lanes that touch rows a fixed stride apart (4 to
+// 32 rows) land in different LDS banks.  The map is its own inverse.  IIB and
+// IIIB postings store this slot for their row.
+__device__ __forceinline__ uint32_t swz(uint32_t s) { return s ^ ((s >> 5) & 31u); }
+
 // Block-wide exclusive scan of one uint32 per thread (kBlock threads).
 // `tmp` needs kBlock / kWave + 1 words of shared memory.  Returns the exclusive
 // prefix; *total gets the block sum.

@@ -323,14 +323,14 @@ __global__ __launch_bounds__(kBlock) void k_iibh_tiles(int32_t t0, int32_t t1, i
   }
   __syncthreads();
   const uint32_t n_tail = gs.pre[Q];
-  // tail list g (< n_tail) of the group: dimension and (slot << 8) | weight
+  // tail list g (< n_tail) of the group: dimension and (score-row offset << 8) | weight
   auto tail_list = [&](uint32_t g, int32_t* d, uint32_t* w) {
     int i = 0;
 #pragma unroll
     for (int x = 1; x < Q; ++x) i += g >= gs.pre[x];
     const int64_t at = gs.tb[i] + (g - gs.pre[i]);
     *d = hj_d[at];
-    *w = (uint32_t(i) << 8) | hj_w[at];
+    *w = (uint32_t(i * stride) << 8) | hj_w[at];
   };
   // the first kSegChunk tail lists stay in registers for all tiles
   int32_t d0 = 0;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_iibh_tiles(int32_t t0, int32_t t1, i
         l = 0;
       }
       const uint32_t total = stage_write<uint32_t>(stage, tmp, n, b, l, w);
-      walk_lists<uint8_t, uint32_t, true>(acc, stage, n, total, P, stride);
+      walk_lists<uint8_t, uint32_t, true>(acc, stage, n, total, P);
       if (slots) walked += block_sum(threadIdx.x < n ? l : 0u, tmp);
       __syncthreads();
     }

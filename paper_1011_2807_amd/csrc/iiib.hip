@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kWave) void k_split_scatter(int64_t n_s, int32_t n_
     if constexpr (sizeof(V) == 1) {
       d = f >> 14;
       lvl = f & 63u;
-      payload = (s_local << 16) | (((f >> 6) & 0xffu) << 8) | lvl;
+      payload = (swz(s_local) << 16) | (((f >> 6) & 0xffu) << 8) | lvl;
     } else {
       d = f >> 6;
       lvl = f & 63u;
@@ -288,7 +288,7 @@ __global__ void k_finalize_iiib_f32(const uint64_t* __restrict__ rec, int64_t n,
   const int64_t step = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
     const uint64_t x = rec[i];
-    ps[i] = uint16_t((x >> 32) & 0xffffu);
+    ps[i] = uint16_t(swz(uint32_t(x >> 32) & 0xffffu));
     pw[i] = __uint_as_float(uint32_t(x));
   }
 }

@@ -268,12 +268,14 @@ __global__ void k_sort_large(const int64_t* __restrict__ offsets, const int64_t*
 }
 
 // ---------------------------------------------------------------- finalize
-// grid-stride (capped grid: a dispatch counts its work-items in 32 bits)
+// Packed entries keep the row's score slot swz(s_local) (the swizzled local-memory
+// slot the join accumulates into), so the walk adds at the stored slot directly.
+// Grid-stride (capped grid: a dispatch counts its work-items in 32 bits).
 __global__ void k_finalize_u8(const uint64_t* __restrict__ rec, int64_t n, uint32_t* __restrict__ post) {
   const int64_t step = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
     const uint64_t x = rec[i];
-    post[i] = (uint32_t(x >> 32) << 16) | ((uint32_t(x) & 0xffu) << 8);
+    post[i] = (swz(uint32_t(x >> 32)) << 16) | ((uint32_t(x) & 0xffu) << 8);
   }
 }
 
@@ -282,7 +284,7 @@ __global__ void k_finalize_f32(const uint64_t* __restrict__ rec, int64_t n, uint
   const int64_t step = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
     const uint64_t x = rec[i];
-    ps[i] = uint16_t(x >> 32);
+    ps[i] = uint16_t(swz(uint32_t(x >> 32)));
     pw[i] = __uint_as_float(uint32_t(x));
   }
 }

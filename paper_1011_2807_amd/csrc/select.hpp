@@ -103,11 +103,6 @@ __device__ uint32_t radix_select(int n, uint32_t want, bool desc, ValF val, Pred
   return prefix;
 }
 
-// Slot of row s_local in a swizzled score array: the low five address bits are
-// XORed with the next five, so lanes that touch rows a fixed stride apart (4 to
-// 32 rows) land in different LDS banks.  The map is its own inverse.
-__device__ __forceinline__ uint32_t swz(uint32_t s) { return s ^ ((s >> 5) & 31u); }
-
 // acc[0..n): scores; slot i holds row s_base + (SWZ ? swz(i) : i), rows past the
 // tile's end hold 0.  The running list of this query lives in o_ids / o_sc
 // (k slots) and *o_cnt.

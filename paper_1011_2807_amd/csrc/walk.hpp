@@ -92,14 +92,14 @@ __device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int6
 // team t takes the t-th of 32 contiguous ranges of groups and its lanes take
 // groups start + i, start + i + 8, ...  A group is one aligned 16-byte load of
 // four entries, so one team load is one 128-byte line.  Entries inside the
-// list's range are added into acc (swizzled slots) with local-memory atomics.
+// list's range are added into acc at the slot they carry (the swizzled slot of
+// their row, stored by the index build) with local-memory atomics.
 // A lane only steps over the lists inside its team's range.
 // kMulti (uint8 only): the lists belong to several queries; a list's weight
-// word is (slot << 8) | w and its scores go to acc + slot * acc_stride.
+// word is (base << 8) | w and its scores go to acc + base (the query's score row).
 constexpr int kTeam = 8;
 template <typename V, typename S, bool kMulti = false>
-__device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P,
-                                           int acc_stride = 0) {
+__device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P) {
   constexpr int U = 4;
   const uint32_t* pre = reinterpret_cast<const uint32_t*>(stage + kPreOff);
   const int64_t* cbase = reinterpret_cast<const int64_t*>(stage + kCbOff);
@@ -161,22 +161,22 @@ __device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_list
       if constexpr (sizeof(V) == 1) {
         const uint32_t x[4] = {e[u].x, e[u].y, e[u].z, e[u].w};
         if constexpr (kMulti) {
-          S* a = acc + size_t(ww[u] >> 8) * acc_stride;
+          S* a = acc + (ww[u] >> 8);
           const uint32_t wq = ww[u] & 0xffu;
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&a[swz(x[i] >> 16)], wq * ((x[i] >> 8) & 0xffu));
+            if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&a[x[i] >> 16], wq * ((x[i] >> 8) & 0xffu));
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[swz(x[i] >> 16)], ww[u] * ((x[i] >> 8) & 0xffu));
+            if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[x[i] >> 16], ww[u] * ((x[i] >> 8) & 0xffu));
         }
       } else {
         const uint32_t sx[4] = {es[u].x & 0xffffu, es[u].x >> 16, es[u].y & 0xffffu, es[u].y >> 16};
         const float wx[4] = {ew[u].x, ew[u].y, ew[u].z, ew[u].w};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[swz(sx[i])], ww[u] * wx[i]);
+          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[sx[i]], ww[u] * wx[i]);
       }
     }
   }

@@ -1,5 +1,5 @@
-"""The autotuner times real joins, picks the fastest tile width, and caches it;
-the tuned join stays exact."""
+"""The autotuner times real joins, picks the fastest tile width (and dense head),
+and caches it; the tuned join stays exact."""
 import os
 
 import pytest
@@ -25,12 +25,14 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch):
     dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
     res = autotune.tune(dS, dR, 10, algo="iib", tiles=(1024, 4096), verbose=True)
     assert res["tile_width"] in (1024, 4096)
-    assert len(res["timings"]) == 4
+    # per tile: plain walk with tile launches and persistent, dense head 128 and 192
+    assert len(res["timings"]) == 8
+    assert res["dense_head"] in (0, 128, 192)
     assert min(t["ms"] for t in res["timings"]) == res["ms"]
     assert os.path.exists(tmp_path / "tune.json")
     again = autotune.tune(dS, dR, 10, algo="iib", tiles=(1024, 4096))
     assert again == res                       # served from the cache
-    ix = kj.build_index(dS, tile_width=res["tile_width"])
+    ix = kj.build_index(dS, tile_width=res["tile_width"], dense_head=res["dense_head"])
     got = kj.knn_join(ix, dR, 10, persistent=res["persistent"])
     torch.cuda.synchronize()
     assert_exact(got, oracle.bf_topk(R, S, 10), "tuned IIB")

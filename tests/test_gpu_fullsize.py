@@ -1,6 +1,7 @@
 """Full-size runs in the configuration bench.py times (medium workload: 100,000
-queries x 1,000,000 vectors, T = 4096): sampled queries against the oracle one
-by one, and properties that must hold for every query."""
+queries x 1,000,000 vectors, T = 2048, dense head of 128 dimensions, four tiles
+per launch): sampled queries against the oracle one by one, and properties that
+must hold for every query."""
 import numpy as np
 import pytest
 
@@ -43,17 +44,24 @@ def test_medium_full_size_sampled_parity():
     R = synth.make("medium", "R")
     k = 10
     print("medium full size generated", flush=True)
-    ix = kj.build_index(kj.DeviceCSR.from_host(S))
+    ix = kj.build_index(kj.DeviceCSR.from_host(S), tile_width=2048, dense_head=128)
     dR = kj.DeviceCSR.from_host(R)
-    got = kj.knn_join(ix, dR, k)
+    got = kj.knn_join(ix, dR, k, tiles_per_launch=4)
     torch.cuda.synchronize()
-    print("IIB done", flush=True)
+    print("IIB (dense head) done", flush=True)
     _invariants(*got, k, S.n_rows)
     assert int(got[2].min()) == k          # every medium query has >= 10 positive scores
+    # random queries plus the longest and the shortest one
     rng = np.random.default_rng(11)
-    rows = np.sort(rng.choice(R.n_rows, 12, replace=False))
+    nnz = np.diff(R.indptr)
+    rows = np.unique(np.concatenate([rng.choice(R.n_rows, 12, replace=False), [nnz.argmax(), nnz.argmin()]]))
     want = oracle.bf_topk_rows(R, S, k, rows)
     assert_exact(tuple(x[torch.from_numpy(rows).cuda()] for x in got), want, "medium full-size IIB")
+    plain = kj.knn_join(ix, dR, k, dense_head=False)
+    torch.cuda.synchronize()
+    for a, b in zip(got, plain):
+        assert torch.equal(a, b)
+    print("plain walk identical", flush=True)
     ref = kj.knn_join(ix, dR, k, algo="iiib", bound_filter=True, level_drop=4)
     torch.cuda.synchronize()
     for a, b in zip(got, ref):
