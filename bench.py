@@ -363,7 +363,8 @@ def run_batched(a):
     tune_iib = autotune.tune(dS, sample, 10, algo="iib", tiles=(2048, 4096, 8192))
     tune_iiib = autotune.tune(dS, sample, 10, algo="iiib", tiles=(tune_iib["tile_width"],), drops=(2, 4, 6))
     _log("autotune %.1fs: IIB %s, IIIB %s" % (time.time() - tt,
-                                             {x: tune_iib[x] for x in ("tile_width", "dense_head", "persistent")},
+                                             {x: tune_iib[x] for x in ("tile_width", "dense_head", "tiles_per_launch",
+                                                                       "persistent")},
                                              {x: tune_iiib[x] for x in ("tile_width", "level_drop")}))
     ix = kj.build_index(dS, tile_width=tune_iib["tile_width"], dense_head=tune_iib["dense_head"])
     stream = torch.cuda.current_stream()
@@ -375,14 +376,15 @@ def run_batched(a):
     # IIB, k = 10 (validated warmup run, then one timed run)
     ref = outs(10)
     stats = torch.zeros(8, dtype=torch.int64, device=dev)
-    kj.knn_join(ix, dR, 10, out=ref, stats=stats, persistent=tune_iib["persistent"])
+    jkw = dict(persistent=tune_iib["persistent"], tiles_per_launch=tune_iib["tiles_per_launch"])
+    kj.knn_join(ix, dR, 10, out=ref, stats=stats, **jkw)
     torch.cuda.synchronize()
     # postings the method processes (Eq. 4's second term): sum over the queries'
     # features of |I_d| (with a dense head the walk counter sees only the tail)
     walked = int(ix.list_lengths().to(torch.int64)[dR.indices.long()].sum().item())
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    kj.knn_join(ix, dR, 10, out=ref, validate=False, stream=stream, persistent=tune_iib["persistent"])
+    kj.knn_join(ix, dR, 10, out=ref, validate=False, stream=stream, **jkw)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_iib = e0.elapsed_time(e1)
@@ -417,7 +419,7 @@ def run_batched(a):
     qps = n_r / (ms_iib / 1e3)
     entry_bytes = 4
     head = tune_iib["dense_head"]
-    launches = ix.n_tiles if not head else -(-ix.n_tiles // 4)
+    launches = ix.n_tiles if not head else -(-ix.n_tiles // (tune_iib["tiles_per_launch"] or 4))
     achieved = walked * entry_bytes / (ms_iib / 1e3) / 1e9
     res = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,

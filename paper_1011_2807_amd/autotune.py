@@ -5,7 +5,8 @@ query sample) and keeps the fastest:
 
 * tile width T (rows of S per tile: the LDS score array and the list split),
 * for IIB on uint8 data, the dense head (0 = plain walk, or the number of
-  longest-list dimensions kept as dense per-tile blocks),
+  longest-list dimensions kept as dense per-tile blocks) and, with a head, the
+  S tiles per launch,
 * schedule (one launch per tile, or the persistent work-queue launch),
 * for IIIB, the level drop of the refined variant.
 
@@ -26,7 +27,7 @@ import torch
 from . import knnj as kj
 
 DEFAULT_TILES = (2048, 4096, 8192)
-CACHE_VERSION = 2  # bumped when the candidate set changes
+CACHE_VERSION = 3  # bumped when the candidate set changes
 
 
 def _cache_path() -> str:
@@ -78,12 +79,13 @@ def _time(fn, reps: int = 2) -> float:
 
 
 def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", tiles: Iterable[int] = DEFAULT_TILES,
-         drops: Iterable[int] = (0, 2, 4, 6), heads: Iterable[int] = (0, 128, 192), use_cache: bool = True,
-         verbose: bool = False) -> Dict:
+         drops: Iterable[int] = (0, 2, 4, 6), heads: Iterable[int] = (0, 128, 192),
+         tiles_per_launch: Iterable[int] = (2, 4, 8), use_cache: bool = True, verbose: bool = False) -> Dict:
     """Fastest settings for joining queries like R_sample against S.
 
-    Returns {"tile_width", "dense_head", "persistent", "level_drop", "ms",
-    "timings"}; the index must then be built with tile_width and dense_head.
+    Returns {"tile_width", "dense_head", "tiles_per_launch", "persistent",
+    "level_drop", "ms", "timings"}; the index must then be built with
+    tile_width and dense_head.
     R_sample should hold a few thousand queries drawn like the real ones.
     """
     key = signature(S, R_sample, k, algo)
@@ -106,7 +108,7 @@ def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", til
             if algo == "iiib":
                 cands = [dict(bound_filter=True, level_drop=d) for d in drops]
             elif h:
-                cands = [dict()]
+                cands = [dict(tiles_per_launch=g) for g in tiles_per_launch]
             else:
                 cands = [dict(persistent=False), dict(persistent=True)]
             for c in cands:
@@ -124,6 +126,7 @@ def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", til
     if best is None:
         raise RuntimeError("autotune: no candidate ran")
     res = {"tile_width": best["tile_width"], "dense_head": int(best.get("dense_head", 0)),
+           "tiles_per_launch": int(best.get("tiles_per_launch", 0)),
            "persistent": bool(best.get("persistent", False)),
            "level_drop": int(best.get("level_drop", 0)), "bound_filter": bool(best.get("bound_filter", False)),
            "ms": best["ms"], "timings": timings, "signature": key}

@@ -26,14 +26,15 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch):
     res = autotune.tune(dS, dR, 10, algo="iib", tiles=(1024, 4096), verbose=True)
     assert res["tile_width"] in (1024, 4096)
     # per tile: plain walk with tile launches and persistent, dense head 128 and 192
-    assert len(res["timings"]) == 8
+    # with 2, 4 and 8 tiles per launch
+    assert len(res["timings"]) == 2 * (2 + 2 * 3)
     assert res["dense_head"] in (0, 128, 192)
     assert min(t["ms"] for t in res["timings"]) == res["ms"]
     assert os.path.exists(tmp_path / "tune.json")
     again = autotune.tune(dS, dR, 10, algo="iib", tiles=(1024, 4096))
     assert again == res                       # served from the cache
     ix = kj.build_index(dS, tile_width=res["tile_width"], dense_head=res["dense_head"])
-    got = kj.knn_join(ix, dR, 10, persistent=res["persistent"])
+    got = kj.knn_join(ix, dR, 10, persistent=res["persistent"], tiles_per_launch=res["tiles_per_launch"])
     torch.cuda.synchronize()
     assert_exact(got, oracle.bf_topk(R, S, 10), "tuned IIB")
     r2 = autotune.tune(dS, dR, 10, algo="iiib", tiles=(2048,), drops=(0, 4))

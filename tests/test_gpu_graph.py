@@ -107,3 +107,42 @@ def test_graph_learned_iiib_pipeline():
             for a, b in zip(outs[k], ref[k]):
                 assert torch.equal(a, b), (rep, k)
     print("miss rate in the graph: %.3f" % float(fb.float().mean()), flush=True)
+
+
+def test_graph_dense_head_replays():
+    """The dense-head IIB join (per-join query preparation, group kernels over
+    runs of tiles) captured with k = 1 and k = 10; replays with eager work in
+    between equal the eager result and the oracle."""
+    S = synth.make("medium", "S", n_rows=30_000)
+    R = synth.make("medium", "R", n_rows=300)
+    dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+    ix = kj.build_index(dS, tile_width=2048, dense_head=128)
+    n = R.n_rows
+    outs = {k: (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+                torch.empty((n, k), dtype=torch.int32, device="cuda"),
+                torch.empty(n, dtype=torch.int32, device="cuda")) for k in (1, 10)}
+    # eager reference (also grows the join scratch outside the capture)
+    eager = {k: [x.clone() for x in kj.knn_join(ix, dR, k, tiles_per_launch=4)] for k in (1, 10)}
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for k in (1, 10):
+            kj.knn_join(ix, dR, k, validate=False, out=outs[k], tiles_per_launch=4)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in (1, 10):
+            for x in outs[k]:
+                x.fill_(-7)
+        kj.knn_join(ix, dR, 3, dense_head=False)      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in (1, 10):
+            for a, b in zip(outs[k], eager[k]):
+                assert torch.equal(a, b), (rep, k)
+    assert torch.equal(outs[1][0][:, 0], outs[10][0][:, 0])
+    rows = list(range(0, n, 30))
+    want = oracle.bf_topk_rows(R, S, 10, rows)
+    assert_exact(tuple(x[rows] for x in outs[10]), want, "graph replay, dense head, k=10")
