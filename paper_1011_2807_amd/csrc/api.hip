@@ -35,7 +35,7 @@ knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32
 size_t head_smem_bytes(int tile, int k, int H);
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st);
-size_t tile_smem_bytes(int tile);
+size_t tile_smem_bytes(int tile, int k, size_t acc_b);
 
 static knnj_status check_csr_host(const knnj_csr* m, const char* name) {
   if (!m) return fail(KNNJ_EINVAL, std::string(name) + " is NULL");
@@ -123,7 +123,7 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
   int dev = 0;
   KNNJ_HIP(hipGetDevice(&dev));
   const int max_smem = device_max_smem(dev);
-  if (tile_smem_bytes(tile) > size_t(max_smem))
+  if (tile_smem_bytes(tile, kMaxK, acc_bytes(S->dtype)) > size_t(max_smem))
     return fail(KNNJ_EUNSUPPORTED, "tile_width too large for this device's local memory (" +
                                        std::to_string(max_smem) + " bytes per workgroup)");
   const int head = opt ? opt->dense_head : 0;

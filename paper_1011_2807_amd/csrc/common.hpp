@@ -102,6 +102,21 @@ template <>
 struct ScoreOf<float> {
   using T = float;
 };
+// Type of the local-memory score map of the IIB / IIIB tile kernels: exact
+// uint32 sums for uint8 data; fp64 for float32 data (a product of two floats is
+// exact in fp64, and fp64 local-memory atomics run far faster on gfx950 than
+// fp32 ones).  Selection and outputs use the fp32 rounding of each fp64 sum.
+template <typename V>
+struct AccOf;
+template <>
+struct AccOf<uint8_t> {
+  using T = uint32_t;
+};
+template <>
+struct AccOf<float> {
+  using T = double;
+};
+inline size_t acc_bytes(int dtype) { return dtype == KNNJ_U8 ? 4 : 8; }
 
 __device__ __forceinline__ uint32_t score_bits(uint32_t v) { return v; }
 __device__ __forceinline__ uint32_t score_bits(float v) { return __float_as_uint(v); }

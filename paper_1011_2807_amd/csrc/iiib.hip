@@ -341,6 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
     int32_t r_hash_log2, int32_t* __restrict__ out_ids, typename ScoreOf<V>::T* __restrict__ out_sc,
     int32_t* __restrict__ out_cnt, uint64_t* __restrict__ slots) {
   using S = typename ScoreOf<V>::T;
+  using A = typename AccOf<V>::T;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint32_t tmp[kBlock / kWave + 1];
   int64_t q;
@@ -351,19 +352,21 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
     q = order ? int64_t(order[q0 + blockIdx.x]) : q0 + blockIdx.x;
   }
   const int T = 1 << log2_tile;
-  S* acc = reinterpret_cast<S*>(smem);
+  A* acc = reinterpret_cast<A*>(smem);
   // r for the completion: a dense array over the dimensions, or (large n_dims,
   // r_hash_log2 > 0) an open-addressing table keyed by d in local memory
   using RW = typename std::conditional<sizeof(V) == 1, uint8_t, float>::type;
   const size_t rbytes = r_region_bytes(n_dims, sizeof(RW), r_hash_log2);
-  RW* rdense = reinterpret_cast<RW*>(smem + size_t(T) * 4);
-  RHash<RW> rh{reinterpret_cast<int32_t*>(smem + size_t(T) * 4),
-               reinterpret_cast<RW*>(smem + size_t(T) * 4 + (size_t(4) << (r_hash_log2 > 0 ? r_hash_log2 : 0))),
+  const size_t abytes = size_t(T) * sizeof(A);
+  RW* rdense = reinterpret_cast<RW*>(smem + abytes);
+  RHash<RW> rh{reinterpret_cast<int32_t*>(smem + abytes),
+               reinterpret_cast<RW*>(smem + abytes + (size_t(4) << (r_hash_log2 > 0 ? r_hash_log2 : 0))),
                r_hash_log2};
-  char* stage = smem + size_t(T) * 4 + rbytes;
+  char* stage = smem + abytes + rbytes;
   const int64_t s_base = int64_t(tile) << log2_tile;
 
-  for (int i = threadIdx.x; i < T / 4; i += kBlock) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
+  for (int i = threadIdx.x; i < int(abytes / 16); i += kBlock)
+    reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
   if (r_hash_log2 > 0) {
     for (int i = threadIdx.x; i < (1 << r_hash_log2); i += kBlock) rh.key[i] = -1;
   } else {
@@ -399,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
   for (int64_t cb = rb; cb < re; cb += kSegChunk) {
     const int n = int(re - cb < kSegChunk ? re - cb : kSegChunk);
     const uint32_t total = stage_lists<V, S>(stage, tmp, key0, r_idx, r_val, cb, n, offsets, cut, lambda);
-    walk_lists<V, S>(acc, stage, n, total, P);
+    walk_lists<V, S, false, A>(acc, stage, n, total, P);
     if (slots) {
       uint32_t l = threadIdx.x < n ? reinterpret_cast<const uint32_t*>(stage + kMetaOff)[threadIdx.x] >> 2 : 0u;
       walked += block_sum(l, tmp);
@@ -413,16 +416,16 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
   if (lambda > 0) {
     const S tau = tau_of(lambda, S(0));
     for (int a = threadIdx.x; a < T; a += kBlock) {
-      const S v = acc[a];
-      if (v == S(0)) continue;
-      if (bound_filter && v + tau <= theta) {
+      const A v = acc[a];
+      if (v == A(0)) continue;
+      if (bound_filter && v + A(tau) <= A(theta)) {
         // A[s] + (bound of the unindexed part, < tau) < theta: s cannot reach theta
-        acc[a] = S(0);
+        acc[a] = A(0);
         continue;
       }
       const int64_t row = s_base + int64_t(swz(uint32_t(a)));
       const int64_t e1 = s_ptr[row + 1];
-      S sum = S(0);
+      A sum = A(0);
       int64_t e = s_ptr[row];
       for (; e < e1; ++e) {
         const uint32_t f = fwd[e];
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
           sum += uint32_t(r_hash_log2 > 0 ? rh.find(int32_t(d)) : rdense[d]) * ((f >> 6) & 0xffu);
         } else {
           const uint32_t d = f >> 6;
-          sum += (r_hash_log2 > 0 ? rh.find(int32_t(d)) : rdense[d]) * fwd_w[e];
+          sum += A(r_hash_log2 > 0 ? rh.find(int32_t(d)) : rdense[d]) * A(fwd_w[e]);
         }
       }
       acc[a] = v + sum;
@@ -441,7 +444,8 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
     }
     __syncthreads();
   }
-  tile_select<S, true>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q, select_smem(stage, k, tmp));
+  tile_select<S, true, A>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q,
+                          select_smem(stage, k, tmp));
   if (slots) {
     const uint32_t c1 = block_sum(n_cand, tmp);
     const uint32_t c2 = block_sum(n_compl, tmp);
@@ -502,7 +506,7 @@ __global__ void k_sort_small(const int64_t* __restrict__ offsets, int64_t n_keys
                              int64_t* __restrict__ big, uint32_t* __restrict__ n_big);
 __global__ void k_sort_mid(const int64_t* __restrict__ offsets, const int64_t* __restrict__ big,
                            const uint32_t* __restrict__ n_big, uint64_t* __restrict__ rec);
-size_t tile_smem_bytes(int tile, int k);
+size_t tile_smem_bytes(int tile, int k, size_t acc_b);
 
 constexpr unsigned kSortGrid = 4096;  // workgroups striding over the queued long lists
 
@@ -551,7 +555,8 @@ static int32_t r_hash_log2(const Index* ix, int32_t max_r) {
 }
 
 static size_t iiib_smem(const Index* ix, int k, int32_t hash_lg) {
-  return tile_smem_bytes(ix->tile, k) + r_region_bytes(ix->n_dims, ix->dtype == KNNJ_U8 ? 1 : 4, hash_lg);
+  return tile_smem_bytes(ix->tile, k, acc_bytes(ix->dtype)) +
+         r_region_bytes(ix->n_dims, ix->dtype == KNNJ_U8 ? 1 : 4, hash_lg);
 }
 
 // Builds the IIIB index of R rows [r0, r1) into ix->iiib_*.  Enqueues kernels only.

@@ -12,8 +12,8 @@
 
 namespace knnj {
 
-size_t tile_smem_bytes(int tile, int k) { return size_t(tile) * 4 + stage_bytes(k); }
-size_t tile_smem_bytes(int tile) { return tile_smem_bytes(tile, kMaxK); }
+// local memory of the IIB tile kernels: score map (acc_b bytes per row) + stage
+size_t tile_smem_bytes(int tile, int k, size_t acc_b) { return size_t(tile) * acc_b + stage_bytes(k); }
 
 __global__ void k_init_out(int64_t n, int32_t* ids, uint32_t* sc, int64_t n_rows, int32_t* cnt) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -46,19 +46,21 @@ __device__ __forceinline__ uint64_t iib_item(int32_t tile, int64_t q, int32_t lo
                                              const V* __restrict__ r_val, const int64_t* __restrict__ offsets,
                                              Postings<V> P, int32_t* __restrict__ out_ids,
                                              typename ScoreOf<V>::T* __restrict__ out_sc, int32_t* __restrict__ out_cnt,
-                                             bool count, typename ScoreOf<V>::T* acc, char* stage, uint32_t* tmp) {
+                                             bool count, typename AccOf<V>::T* acc, char* stage, uint32_t* tmp) {
   using S = typename ScoreOf<V>::T;
+  using A = typename AccOf<V>::T;
   const int T = 1 << log2_tile;
   const int64_t s_base = int64_t(tile) << log2_tile;
   // rows past the end of S have no postings, so their slots stay 0
-  for (int i = threadIdx.x; i < T / 4; i += kBlock) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
+  for (int i = threadIdx.x; i < int(T * sizeof(A) / 16); i += kBlock)
+    reinterpret_cast<uint4*>(acc)[i] = make_uint4(0, 0, 0, 0);
   const int64_t rb = r_ptr[q], re = r_ptr[q + 1];
   const int64_t key0 = int64_t(tile) * n_dims;
   uint64_t walked = 0;
   for (int64_t cb = rb; cb < re; cb += kSegChunk) {
     const int n = int(re - cb < kSegChunk ? re - cb : kSegChunk);
     const uint32_t total = stage_lists<V, S>(stage, tmp, key0, r_idx, r_val, cb, n, offsets);
-    walk_lists<V, S>(acc, stage, n, total, P);
+    walk_lists<V, S, false, A>(acc, stage, n, total, P);
     if (count) {
       // exact entries walked: sum of list lengths of this pass
       uint32_t l = threadIdx.x < n ? reinterpret_cast<const uint32_t*>(stage + kMetaOff)[threadIdx.x] >> 2 : 0u;
@@ -66,7 +68,8 @@ __device__ __forceinline__ uint64_t iib_item(int32_t tile, int64_t q, int32_t lo
     }
     __syncthreads();
   }
-  tile_select<S, true>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q, select_smem(stage, k, tmp));
+  tile_select<S, true, A>(acc, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q,
+                          select_smem(stage, k, tmp));
   return walked;
 }
 
@@ -80,12 +83,12 @@ __global__ __launch_bounds__(kBlock) void k_iib_tile(int32_t tile, int32_t log2_
                                                      int32_t* __restrict__ out_ids,
                                                      typename ScoreOf<V>::T* __restrict__ out_sc,
                                                      int32_t* __restrict__ out_cnt, uint64_t* __restrict__ slots) {
-  using S = typename ScoreOf<V>::T;
+  using A = typename AccOf<V>::T;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint32_t tmp[kBlock / kWave + 1];
   (void)n_s;
-  S* acc = reinterpret_cast<S*>(smem);
-  char* stage = smem + (size_t(4) << log2_tile);
+  A* acc = reinterpret_cast<A*>(smem);
+  char* stage = smem + (sizeof(A) << log2_tile);
   const int64_t q = order ? int64_t(order[q0 + blockIdx.x]) : q0 + blockIdx.x;
   const uint64_t walked = iib_item<V>(tile, q, log2_tile, n_dims, k, r_ptr, r_idx, r_val, offsets, P,
                                       out_ids, out_sc, out_cnt, slots != nullptr, acc, stage, tmp);
@@ -103,12 +106,12 @@ __global__ __launch_bounds__(kBlock) void k_iib_persistent(Sched sch, int32_t ti
                                                            int32_t* __restrict__ out_ids,
                                                            typename ScoreOf<V>::T* __restrict__ out_sc,
                                                            int32_t* __restrict__ out_cnt, uint64_t* __restrict__ slots) {
-  using S = typename ScoreOf<V>::T;
+  using A = typename AccOf<V>::T;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint32_t tmp[kBlock / kWave + 1];
   __shared__ uint32_t slot[1];
-  S* acc = reinterpret_cast<S*>(smem);
-  char* stage = smem + (size_t(4) << log2_tile);
+  A* acc = reinterpret_cast<A*>(smem);
+  char* stage = smem + (sizeof(A) << log2_tile);
   uint64_t walked = 0;
   int64_t first, n;
   while (sched_chunk(sch, tile, &first, &n, slot)) {
@@ -193,7 +196,7 @@ static const int64_t kMaxGrid = 1ll << 30;
 
 knnj_status launch_iib(const Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t* ids, void* sc,
                        int32_t* cnt, uint64_t* slots, hipStream_t st) {
-  const size_t smem = tile_smem_bytes(ix->tile, k);
+  const size_t smem = tile_smem_bytes(ix->tile, k, acc_bytes(ix->dtype));
   for (int32_t t = 0; t < ix->n_tiles; ++t) {
     for (int64_t q0 = 0; q0 < R->n_rows; q0 += kMaxGrid) {
       const unsigned g = unsigned(R->n_rows - q0 < kMaxGrid ? R->n_rows - q0 : kMaxGrid);
@@ -226,7 +229,7 @@ static unsigned persistent_grid(K kernel, size_t smem, int device) {
 
 knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k, const Sched& sch, int32_t* ids,
                                   void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st) {
-  const size_t smem = tile_smem_bytes(ix->tile, k);
+  const size_t smem = tile_smem_bytes(ix->tile, k, acc_bytes(ix->dtype));
   if (ix->dtype == KNNJ_U8) {
     Postings<uint8_t> P{reinterpret_cast<const uint4*>(ix->post_u8)};
     const unsigned g = persistent_grid(k_iib_persistent<uint8_t>, smem, ix->device);
@@ -249,7 +252,7 @@ knnj_status launch_iib_persistent(const Index* ix, const knnj_csr* R, int32_t k,
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st) {
   const int log2_tile = 11;
-  const size_t smem = tile_smem_bytes(1 << log2_tile, k);
+  const size_t smem = tile_smem_bytes(1 << log2_tile, k, 4);
   for (int64_t q0 = 0; q0 < R->n_rows; q0 += kMaxGrid) {
     const unsigned g = unsigned(R->n_rows - q0 < kMaxGrid ? R->n_rows - q0 : kMaxGrid);
     if (S->dtype == KNNJ_U8)

@@ -35,6 +35,8 @@ __host__ __device__ inline uint32_t select_bytes(int k) { return select_cap(k) *
 
 __device__ __forceinline__ uint32_t to_bits(uint32_t v) { return v; }
 __device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
+// fp64 sums select by their fp32 rounding (round to nearest: order-preserving)
+__device__ __forceinline__ uint32_t to_bits(double v) { return __float_as_uint(float(v)); }
 template <typename S>
 __device__ __forceinline__ S from_bits(uint32_t b);
 template <>
@@ -106,8 +108,8 @@ __device__ uint32_t radix_select(int n, uint32_t want, bool desc, ValF val, Pred
 // acc[0..n): scores; slot i holds row s_base + (SWZ ? swz(i) : i), rows past the
 // tile's end hold 0.  The running list of this query lives in o_ids / o_sc
 // (k slots) and *o_cnt.
-template <typename S, bool SWZ>
-__device__ void tile_select(const S* acc, int n_valid, int64_t s_base, int k, int32_t* __restrict__ o_ids,
+template <typename S, bool SWZ, typename A = S>
+__device__ void tile_select(const A* acc, int n_valid, int64_t s_base, int k, int32_t* __restrict__ o_ids,
                             S* __restrict__ o_sc, int32_t* __restrict__ o_cnt, const SelectSmem& sm) {
   const int cnt = *o_cnt;
   const uint32_t theta = cnt == k ? to_bits(o_sc[k - 1]) : 0u;

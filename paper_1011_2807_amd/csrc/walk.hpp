@@ -98,8 +98,10 @@ __device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int6
 // kMulti (uint8 only): the lists belong to several queries; a list's weight
 // word is (base << 8) | w and its scores go to acc + base (the query's score row).
 constexpr int kTeam = 8;
-template <typename V, typename S, bool kMulti = false>
-__device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P) {
+// A: type of the score map (the staged weights are S; float lists accumulate
+// into fp64).
+template <typename V, typename S, bool kMulti = false, typename A = S>
+__device__ __forceinline__ void walk_lists(A* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P) {
   constexpr int U = 4;
   const uint32_t* pre = reinterpret_cast<const uint32_t*>(stage + kPreOff);
   const int64_t* cbase = reinterpret_cast<const int64_t*>(stage + kCbOff);
@@ -161,7 +163,7 @@ __device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_list
       if constexpr (sizeof(V) == 1) {
         const uint32_t x[4] = {e[u].x, e[u].y, e[u].z, e[u].w};
         if constexpr (kMulti) {
-          S* a = acc + (ww[u] >> 8);
+          A* a = acc + (ww[u] >> 8);
           const uint32_t wq = ww[u] & 0xffu;
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -176,7 +178,7 @@ __device__ __forceinline__ void walk_lists(S* acc, const char* stage, int n_list
         const float wx[4] = {ew[u].x, ew[u].y, ew[u].z, ew[u].w};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[sx[i]], ww[u] * wx[i]);
+          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[sx[i]], A(ww[u]) * A(wx[i]));
       }
     }
   }
