@@ -308,18 +308,23 @@ __global__ __launch_bounds__(kBlock) void k_iibh_tiles(int32_t t0, int32_t t1, i
   uint32_t* acc = reinterpret_cast<uint32_t*>(smem);                        // [Q][stride]
   uint4* rh = reinterpret_cast<uint4*>(smem + size_t(Q) * stride * 4);      // [Q][HC]
   char* stage = smem + size_t(Q) * stride * 4 + size_t(Q) * H;
+  // thread i loads query i's state (the loads of the Q queries overlap), then
+  // thread 0 turns the tail counts into their prefix
+  if (threadIdx.x < Q) {
+    const int i = threadIdx.x;
+    const int64_t p = int64_t(blockIdx.x) * Q + i;
+    const int64_t q = p < n_q ? (order ? int64_t(order[p]) : p) : -1;
+    gs.qs[i] = q;
+    gs.tb[i] = q >= 0 ? r_ptr[q] : 0;
+    gs.pre[i + 1] = q >= 0 ? hj_cnt[q] : 0u;
+    const int32_t c = q >= 0 ? out_cnt[q] : 0;
+    gs.cn[i] = c;
+    gs.th[i] = c == k ? out_sc[q * k + k - 1] : 0u;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     gs.pre[0] = 0;
-    for (int i = 0; i < Q; ++i) {
-      const int64_t p = int64_t(blockIdx.x) * Q + i;
-      const int64_t q = p < n_q ? (order ? int64_t(order[p]) : p) : -1;
-      gs.qs[i] = q;
-      gs.tb[i] = q >= 0 ? r_ptr[q] : 0;
-      gs.pre[i + 1] = gs.pre[i] + (q >= 0 ? hj_cnt[q] : 0u);
-      const int32_t c = q >= 0 ? out_cnt[q] : 0;
-      gs.cn[i] = c;
-      gs.th[i] = c == k ? out_sc[q * k + k - 1] : 0u;
-    }
+    for (int i = 0; i < Q; ++i) gs.pre[i + 1] += gs.pre[i];
   }
   __syncthreads();
   const uint32_t n_tail = gs.pre[Q];
