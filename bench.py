@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "exact KNN-join queries/s and postings GB/s vs HBM peak; learned vs plain IIIB"
 HBM_PEAK_GBPS = 8000.0
 LDS_ATOMIC_PEAK = 256 * 2.4e9 * 16
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def _args():
@@ -78,18 +79,19 @@ def _kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_key: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
+def _counters(kernel_key: str):
+    """Per-launch figures of a kernel from committed rocprofv3 counter runs
+    (HBM bytes, VALU instructions), if they were taken on the current kernel
+    sources; else {}."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         tab = json.load(f)
     ent = tab.get(kernel_key)
     if not ent or ent.get("source_hash") != _kernel_hash():
-        return None
-    return ent.get("bytes_per_launch")
+        return {}
+    return ent
 
 
 def _log(*a):
@@ -220,7 +222,8 @@ def main():
     bytes_per_launch = walked * entry_bytes / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
     kname = "k_iibh_tiles" if head else "k_iib_tile"
-    traffic = _traffic("%s/%s/T%d" % (kname, a.workload, ix.tile_width))
+    cnt = _counters("%s/%s/T%d" % (kname, a.workload, ix.tile_width))
+    traffic = cnt.get("bytes_per_launch")
     tail_eps = walked_tail / (ms / 1e3)
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
@@ -230,6 +233,13 @@ def main():
             # wave64 LDS atomic per 4 clocks per CU (16 lane-ops/clk): 256 CUs x 2.4 GHz x 16
             "onchip": {"unit": "LDS atomic lane-ops/s", "achieved": tail_eps, "peak": LDS_ATOMIC_PEAK,
                        "frac": round(tail_eps / LDS_ATOMIC_PEAK, 4)}}
+    if cnt.get("valu_wave_instrs_per_launch"):
+        # vector-ALU issue: the counted VALU wave instructions per launch over the live launch
+        # time, against one wave64 VALU instruction per 4 clocks per SIMD (16 lanes), 4 SIMDs
+        # per CU, 256 CUs, 2.4 GHz
+        vi = cnt["valu_wave_instrs_per_launch"] / (avg_launch_ms / 1e3)
+        roof["valu"] = {"unit": "VALU wave-instructions/s", "achieved": vi, "peak": VALU_ISSUE_PEAK,
+                        "frac": round(vi / VALU_ISSUE_PEAK, 4)}
     if head:
         # bytes of dense head blocks read per launch (the four queries of a workgroup share each read)
         hb = -(-n_r // 4) * ix.tile_width * head * min(G, ix.n_tiles)
