@@ -104,7 +104,7 @@ def main():
         print(_kernel_hash())
         return
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+        print("bench.py runs on one GPU only: the join has no multi-GPU path, so --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -43,7 +43,7 @@ typedef enum {
   KNNJ_ENOMEM = -2,      /* device allocation failed */
   KNNJ_EDEVICE = -3,     /* a HIP runtime call failed */
   KNNJ_EOVERFLOW = -4,   /* an integer score could exceed 2^31 - 1 */
-  KNNJ_EUNSUPPORTED = -5 /* valid input outside what this build handles */
+  KNNJ_EUNSUPPORTED = -5 /* valid input outside what the library supports */
 } knnj_status;
 
 /* Value type of a sparse matrix. */
