@@ -5,9 +5,9 @@
  * The operation (Problem definition, Sec. 3): for every vector r of R, return
  * the k vectors s of S with the largest score dot(r, s) = sum_d r[d] * s[d]
  * (Eq. 1), where a sparse vector is a list of features (d, w), ascending d,
- * w > 0.  Reading used throughout: a neighbour must have score > 0 (the
- * selection rule starts from a pruning score of 0, Algorithm 1 line 3 and
- * Algorithm 2 line 5); neighbours are ordered by (score descending, S row id
+ * w > 0.  Reading used throughout: a neighbour must have score > 0
+ * (Algorithms 1 and 2 start the pruning score at 0 and admit only scores above
+ * it); neighbours are ordered by (score descending, S row id
  * ascending), which also decides ties at the k-th place; a query with fewer
  * than k positive-score vectors gets padding slots (id -1, score 0).
  *
@@ -121,7 +121,7 @@ typedef struct {
   int32_t algo;          /* knnj_algo */
   uint32_t flags;        /* KNNJ_FLAG_* */
   /* IIIB: rows of R per block whose statistics (dimension order and per-dimension
-   * maximum weight, Algorithm 4 lines 6-7) define the refinement bound; 0 means
+   * maximum weight, Algorithm 4's block statistics) define the refinement bound; 0 means
    * all of R is one block. */
   int64_t r_block_rows;
   /* Optional device float[n_rows of R]: a per-query guess of the k-th score used

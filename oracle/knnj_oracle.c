@@ -9,9 +9,8 @@
  *   for every r in R and every s_j in S (ascending j):
  *     v = dot(r, s_j) by the two-pointer merge over ascending dimension ids
  *         (the dot() routine of Algorithm 2);
- *   keep the pairs with v > 0 (the selection rule starts from a pruning score
- *   of 0, Algorithm 1 line 3 and Algorithm 2 line 5, so a zero score is never
- *   a neighbour);
+ *   keep the pairs with v > 0 (Algorithms 1 and 2 start the pruning score at 0
+ *   and admit only scores above it, so a zero score is never a neighbour);
  *   order them by (v descending, j ascending) and return the first min(k, #);
  *   unused output slots are id -1, score 0.
  *

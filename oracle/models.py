@@ -41,10 +41,11 @@ def dot(r: Vec, s: Vec):
 
 
 class Candidates:
-    """The KNN candidate set of one r with its pruneScore (Algorithm 2 lines 5-7).
+    """The KNN candidate set of one r with its pruneScore (the candidate step of
+    Algorithm 2).
 
     pruneScore is the score of the k-th candidate once k are held, else 0
-    (Algorithm 1 line 3 initialises it to 0).  A vector enters only if its
+    (Algorithm 1 initialises it to 0).  A vector enters only if its
     score is strictly greater; the set keeps the k best by (score desc, id asc).
     """
 
@@ -101,12 +102,12 @@ def bnl_join(R: List[Vec], S: List[Vec], k: int, algo: str = "bf", r_block: int 
     stats = dict(postings_walked=0, indexed=0, completion_entries=0, candidates=0, merge_steps=0,
                  fallbacks=[])
     results: List[List[Tuple[float, int]]] = [None] * len(R)  # type: ignore
-    for rb in _blocks(len(R), r_block):                       # Alg. 1 lines 1-2
-        cand = {i: Candidates(k) for i in rb}                  # Alg. 1 line 3
+    for rb in _blocks(len(R), r_block):                       # Alg. 1: outer loop over R blocks
+        cand = {i: Candidates(k) for i in rb}                  # empty lists, pruneScore 0
         theta_max = {i: 0 for i in rb}
-        for sb in _blocks(len(S), s_block):                    # Alg. 1 lines 4-5
+        for sb in _blocks(len(S), s_block):                    # inner loop over S blocks
             _join_blocks(R, S, rb, sb, cand, algo, rule, order_key, seed, max_weight, stats, theta_max)
-        for i in rb:                                           # Alg. 1 line 7
+        for i in rb:                                           # output of the block
             res = cand[i].items
             if seed is not None and (len(res) < k or res[-1][0] < theta_max[i]):
                 stats["fallbacks"].append(i)

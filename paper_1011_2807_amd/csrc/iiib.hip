@@ -1,10 +1,10 @@
 // IIIB: threshold-refined inverted index (Algorithm 4) on the GPU.
 //
 // Per block of R rows (the B_r of Algorithm 1):
-//   k_block_stats   freq_d(B_r) and maxWeight_d(B_r) (Algorithm 4 lines 6-7)
+//   k_block_stats   freq_d(B_r) and maxWeight_d(B_r) (Algorithm 4's block statistics)
 //   k_split_rows    for every s: its features in the block's dimension order
 //                   (frequency in B_r descending, then d ascending), the running
-//                   bound t = sum maxWeight_d * w over that order (lines 8-12),
+//                   bound t = sum maxWeight_d * w over that order (Algorithm 4's split),
 //                   and the level of t on a fixed geometric ladder tau_1 < tau_2 < ...
 //                   (a feature is indexed for a threshold tau_l iff its t >= tau_l).
 //                   Writes the row in that order ("fwd") and counts entries per
@@ -15,8 +15,9 @@
 // Join, per S tile (one workgroup per query; k_iiib_tile):
 //   theta = the query's running pruneScore (or its seed); lambda = level(theta):
 //   walk only the prefix of each list with level >= lambda (the indexed part,
-//   lines 16-19); then for every s with A[s] != 0 add dot(r, s') over the row's
-//   leading features with level < lambda (the unindexed part, line 21); select.
+//   Algorithm 4's accumulation); then for every s with A[s] != 0 add dot(r, s')
+//   over the row's leading features with level < lambda (the unindexed part,
+//   Algorithm 4's completion); select.
 //
 // The split rule is "index once t >= tau" with tau <= theta, so every s whose
 // score reaches theta shares an indexed feature with r (Theorem 1's argument
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_iiib_tile(
     __syncthreads();
   }
 
-  // completion (Algorithm 4 line 21): every s with A[s] != 0 gets dot(r, s') over
+  // completion (Algorithm 4): every s with A[s] != 0 gets dot(r, s') over
   // the leading features of its row whose level is below lambda
   uint32_t n_cand = 0, n_compl = 0;
   if (lambda > 0) {

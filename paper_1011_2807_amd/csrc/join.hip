@@ -1,8 +1,8 @@
 // IIB join (Algorithm 3, Find_Matches_IIB) and the brute-force join
 // (Algorithm 2) on one S tile at a time.
 //
-// One workgroup owns one query r for one tile t.  Its score map A (Algorithm 3
-// line 10) is a dense array acc[T] in local memory indexed by s_local; the
+// One workgroup owns one query r for one tile t.  Its score map A (the map of
+// Algorithm 3) is a dense array acc[T] in local memory indexed by s_local; the
 // postings walk adds r[d] * w to acc[s_local] with local-memory atomics, which
 // are exact for integer scores.  The lists (t, d) of all features of r are
 // walked as one concatenated sequence of 16-byte groups shared out over teams of

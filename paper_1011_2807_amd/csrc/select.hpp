@@ -1,6 +1,6 @@
 // Per-query top-k selection over one S tile's score array held in local
-// memory, merged into the query's running list (Algorithm 2 lines 5-7,
-// Algorithm 3 lines 14-17, Algorithm 4 lines 20-24).
+// memory, merged into the query's running list (the candidate step of
+// Algorithms 2, 3 and 4).
 //
 // Keys: (score bits << 32) | ~id.  For int scores and for positive floats the
 // bit pattern orders like the value, and ~id puts the lower id first among
