@@ -14,8 +14,9 @@ queries and each checked identical to the headline output:
   iib_plain_walk  the same index walked list by list
   iiib.plain    Algorithm 4 as printed (split at the running threshold, every
                 candidate completed)
-  iiib.refined  the same plus the bound-filtered completion and a 4-step level
-                drop (beyond the paper; still exact)
+  iiib.refined  the same plus the bound-filtered completion and a level drop
+                picked by the autotuner on a query sample (beyond the paper;
+                still exact)
   iiib.learned  iiib.refined seeded by the MLP's predicted k-th score (features
                 + prediction + join timed together); miss rate = share of
                 queries whose seed was too high and that were re-run
@@ -27,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -69,13 +71,21 @@ def _args():
 KERNEL_SOURCES = ("common.hpp", "select.hpp", "walk.hpp", "join.hip", "head.hip")
 
 
+def _strip_comments(src: str) -> str:
+    """C++ source without comments and blank-space runs (so a comment edit does
+    not count as a kernel change)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def _kernel_hash() -> str:
-    """Hash of the sources the IIB tile kernels are built from."""
+    """Hash of the code (comments stripped) the IIB tile kernels are built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1011_2807_amd", "csrc")
     for f in KERNEL_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(_strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -281,7 +291,14 @@ def main():
         torch.cuda.synchronize()
         _log("first IIIB join done")
         iiib["plain"] = timed_join("iiib plain")
-        iiib["refined"] = timed_join("iiib refined", bound_filter=True, level_drop=4)
+        # level drop of the refined variants: the autotuner's choice on a 4,000-query sample
+        from paper_1011_2807_amd import autotune
+        sample = kj.DeviceCSR.from_host(R.take_rows(range(min(4000, n_r))))
+        drop = autotune.tune(dS, sample, k, algo="iiib", tiles=(ix.tile_width,), drops=(4, 8, 12, 16, 24),
+                             use_cache=False)["level_drop"]
+        _log("iiib level drop (autotuned): %d" % drop)
+        iiib["level_drop"] = drop
+        iiib["refined"] = timed_join("iiib refined", bound_filter=True, level_drop=drop)
         # learned seed: labels are the exact k-th scores of the training queries
         tt = time.time()
         dT = kj.DeviceCSR.from_host(R_train)
@@ -293,7 +310,7 @@ def main():
         t_train = time.time() - tt
         _log("trained the seed MLP on %d queries in %.1fs, loss %.4f -> %.4f" % (n_train, t_train, losses[0],
                                                                                   losses[-1]))
-        res = timed_join("iiib learned", bound_filter=True, level_drop=4,
+        res = timed_join("iiib learned", bound_filter=True, level_drop=drop,
                          pre=lambda: mlp.predict(kj.Mlp.features(ix, dR, stream=stream), stream=stream))
         res["miss_rate"] = round(res["fallbacks"] / n_r, 4)
         res["train_queries"] = n_train
@@ -371,7 +388,7 @@ def run_batched(a):
     sample = kj.DeviceCSR.from_host(R.take_rows(range(min(4000, n_r))))
     tt = time.time()
     tune_iib = autotune.tune(dS, sample, 10, algo="iib", tiles=(2048, 4096, 8192))
-    tune_iiib = autotune.tune(dS, sample, 10, algo="iiib", tiles=(tune_iib["tile_width"],), drops=(2, 4, 6))
+    tune_iiib = autotune.tune(dS, sample, 10, algo="iiib", tiles=(tune_iib["tile_width"],), drops=(4, 8, 12, 16, 24))
     _log("autotune %.1fs: IIB %s, IIIB %s" % (time.time() - tt,
                                              {x: tune_iib[x] for x in ("tile_width", "dense_head", "tiles_per_launch",
                                                                        "persistent")},

@@ -79,7 +79,7 @@ def _time(fn, reps: int = 2) -> float:
 
 
 def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", tiles: Iterable[int] = DEFAULT_TILES,
-         drops: Iterable[int] = (0, 2, 4, 6), heads: Iterable[int] = (0, 128, 192),
+         drops: Iterable[int] = (0, 4, 8, 12, 16, 24), heads: Iterable[int] = (0, 128, 192),
          tiles_per_launch: Iterable[int] = (2, 4, 8), use_cache: bool = True, verbose: bool = False) -> Dict:
     """Fastest settings for joining queries like R_sample against S.
 
