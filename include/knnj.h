@@ -49,7 +49,7 @@ typedef enum {
 /* Value type of a sparse matrix. */
 typedef enum {
   KNNJ_U8 = 0,  /* uint8 weights in [1, 255]; scores are exact int32 */
-  KNNJ_F32 = 1  /* finite float32 weights > 0; scores are float32 */
+  KNNJ_F32 = 1  /* finite float32 weights > 0; scores are float32 (fp64 sums, rounded) */
 } knnj_dtype;
 
 /* In-memory join algorithm run on each (query group, S tile) pair. */
