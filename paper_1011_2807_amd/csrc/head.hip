@@ -210,15 +210,13 @@ __device__ __forceinline__ void group_select(const uint32_t* acc, int stride, in
   for (int i = 0; i < Q; ++i) {
     if (!hard[i]) continue;
     const int64_t q = qs[i];
-    const SelectSmem sm = select_smem(stage, k, tmp);
     tile_select<uint32_t, true>(acc + size_t(i) * stride, T, s_base, k, out_ids + q * k, out_sc + q * k, out_cnt + q,
-                                sm);
-    // the merged list is still in local memory: m = sm.scal[2] keys, sorted
+                                select_smem(stage, k, tmp));
+    // the running state from the list the selection wrote (it ends with a barrier)
     if (threadIdx.x == 0) {
-      const int m = int(sm.scal[2]);
-      const int keep = m < k ? m : k;
+      const int keep = out_cnt[q];
       cn[i] = keep;
-      th[i] = keep == k ? uint32_t(sm.keys[k - 1] >> 32) : 0u;
+      th[i] = keep == k ? out_sc[q * k + k - 1] : 0u;
     }
     __syncthreads();
   }
