@@ -23,6 +23,15 @@
  * the default stream) unless stated otherwise; output buffers are valid after
  * the stream is synchronised.
  *
+ * Devices and overlap: an index or an MLP is used on the device that was
+ * current when it was made (a call with another device current fails with
+ * EINVAL).  An index holds the scratch memory of its joins (query order,
+ * statistics, IIIB's per-block index), so joins on one index must not overlap:
+ * issue them on one stream, or order them.  A join called with out_count NULL
+ * uses a count buffer of the calling thread on the current device; two such
+ * joins from one thread must not overlap either.  Different indexes may be
+ * joined concurrently.
+ *
  * Errors: every call returns a knnj_status; on failure nothing is written to
  * the outputs (unless stated) and knnj_last_error() returns a message for the
  * calling thread.

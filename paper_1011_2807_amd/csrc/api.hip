@@ -49,6 +49,16 @@ static knnj_status check_csr_host(const knnj_csr* m, const char* name) {
   return KNNJ_OK;
 }
 
+// Objects (index, MLP) are used on the device that was current when they were made.
+knnj_status check_device(int owner, const char* what) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(KNNJ_EDEVICE, "hipGetDevice failed");
+  if (dev != owner)
+    return fail(KNNJ_EINVAL, std::string(what) + " was made on device " + std::to_string(owner) + ", but device " +
+                                 std::to_string(dev) + " is current");
+  return KNNJ_OK;
+}
+
 static int device_max_smem(int dev) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
@@ -101,6 +111,7 @@ using namespace knnj;
 
 namespace knnj {
 const uint32_t* index_list_len(const knnj_index* h) { return reinterpret_cast<const Index*>(h)->list_len; }
+int index_device(const knnj_index* h) { return reinterpret_cast<const Index*>(h)->device; }
 }  // namespace knnj
 
 // The public handle is the internal Index itself, seen through an opaque type.
@@ -215,6 +226,8 @@ knnj_status knnj_index_info_get(const knnj_index* h, knnj_index_info* out) {
 knnj_status knnj_index_list_lengths(const knnj_index* h, uint32_t* out, void* stream) {
   if (!h || !out) return fail(KNNJ_EINVAL, "NULL argument");
   const Index* ix = impl(h);
+  const knnj_status rc = check_device(ix->device, "the index");
+  if (rc != KNNJ_OK) return rc;
   KNNJ_HIP(hipMemcpyAsync(out, ix->list_len, sizeof(uint32_t) * ix->n_dims, hipMemcpyDeviceToDevice,
                           (hipStream_t)stream));
   return KNNJ_OK;
@@ -222,8 +235,13 @@ knnj_status knnj_index_list_lengths(const knnj_index* h, uint32_t* out, void* st
 
 void knnj_index_free(knnj_index* h) {
   if (!h) return;
+  // wait for and free on the index's own device, whichever device is current
+  int cur = -1;
+  const bool other = hipGetDevice(&cur) == hipSuccess && cur != impl(h)->device &&
+                     hipSetDevice(impl(h)->device) == hipSuccess;
   (void)hipDeviceSynchronize();
   free_index(impl(h));
+  if (other) (void)hipSetDevice(cur);
 }
 
 static knnj_status check_join_args(const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t n_dims,
@@ -244,21 +262,36 @@ static knnj_status overflow_check(int32_t dtype, int64_t max_r, int64_t max_s) {
   return KNNJ_OK;
 }
 
-// Count buffer for callers that pass out_count = NULL (grow-only, per thread).
-static int32_t* scratch_count(int64_t n) {
-  static thread_local int32_t* buf = nullptr;
-  static thread_local int64_t cap = 0;
-  if (n > cap) {
-    if (buf) {
+// Grow-only device buffer of at least `bytes` on the current device, one per
+// (calling thread, device, use): the count buffer of joins called with
+// out_count = NULL, and the error words of the brute-force join's validation.
+enum ThreadBuffer { kCountBuffer = 0, kBfErrBuffer = 1 };
+
+static void* thread_buffer(ThreadBuffer use, size_t bytes) {
+  constexpr int kMaxDevices = 64;
+  struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+  };
+  static thread_local Buf bufs[2][kMaxDevices];
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  Buf& b = bufs[use][dev];
+  if (bytes > b.cap) {
+    if (b.p) {
       (void)hipDeviceSynchronize();
-      (void)hipFree(buf);
+      (void)hipFree(b.p);
     }
-    buf = nullptr;
-    cap = 0;
-    if (hipMalloc(&buf, sizeof(int32_t) * n) != hipSuccess) return nullptr;
-    cap = n;
+    b.p = nullptr;
+    b.cap = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) return nullptr;
+    b.cap = bytes;
   }
-  return buf;
+  return b.p;
+}
+
+static int32_t* scratch_count(int64_t n) {
+  return static_cast<int32_t*>(thread_buffer(kCountBuffer, sizeof(int32_t) * size_t(n)));
 }
 
 // Grow the persistent-schedule scratch to n queries (the only allocation of an
@@ -301,8 +334,9 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
   g_last_error.clear();
   if (!h) return fail(KNNJ_EINVAL, "index is NULL");
   Index* ix = impl(h);
-  knnj_status rc = check_join_args(R, k, ids, sc, ix->n_dims, ix->dtype);
+  knnj_status rc = check_device(ix->device, "the index");
   if (rc != KNNJ_OK) return rc;
+  if ((rc = check_join_args(R, k, ids, sc, ix->n_dims, ix->dtype)) != KNNJ_OK) return rc;
   knnj_join_opts o;
   memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
@@ -357,8 +391,8 @@ knnj_status knnj_join_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_
   if (rc != KNNJ_OK) return rc;
   if ((rc = check_join_args(R, k, ids, sc, S->n_dims, S->dtype)) != KNNJ_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
-  static thread_local int32_t* err = nullptr;
-  if (!err && hipMalloc(&err, 4 * sizeof(int32_t)) != hipSuccess) return fail(KNNJ_ENOMEM, "allocation failed");
+  int32_t* err = static_cast<int32_t*>(thread_buffer(kBfErrBuffer, 4 * sizeof(int32_t)));
+  if (!err) return fail(KNNJ_ENOMEM, "allocation failed");
   int32_t max_s = 0, max_r = 0;
   if ((rc = validate_csr(S, err, st, &max_s)) != KNNJ_OK) return rc;
   if ((rc = validate_csr(R, err, st, &max_r)) != KNNJ_OK) return rc;

@@ -307,6 +307,8 @@ __global__ void k_scale(int64_t n, float* __restrict__ y, const float* __restric
 }
 
 const uint32_t* index_list_len(const knnj_index* ix);
+int index_device(const knnj_index* ix);
+knnj_status check_device(int owner, const char* what);
 
 static constexpr size_t kFwdSmem = sizeof(float) * (kIn * kHid + kHid * kHid + kSB * kIn + 2 * kSB * kHid);
 static constexpr size_t kBackSmem = sizeof(float) * (kHid * kHid + kSB * kHid);
@@ -317,6 +319,7 @@ using namespace knnj;
 
 struct knnj_mlp {
   Mlp m;
+  int device;  // the device its buffers live on
 };
 
 extern "C" {
@@ -324,7 +327,10 @@ extern "C" {
 knnj_status knnj_mlp_create(uint64_t seed, knnj_mlp** out) {
   if (!out) return fail(KNNJ_EINVAL, "out is NULL");
   *out = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(KNNJ_EDEVICE, "hipGetDevice failed");
   knnj_mlp* h = new knnj_mlp();
+  h->device = dev;
   Mlp& m = h->m;
   if (hipMalloc(&m.master, sizeof(float) * kParams) != hipSuccess ||
       hipMalloc(&m.work, sizeof(float) * kParams) != hipSuccess ||
@@ -362,6 +368,10 @@ knnj_status knnj_mlp_create(uint64_t seed, knnj_mlp** out) {
 
 void knnj_mlp_free(knnj_mlp* h) {
   if (!h) return;
+  // wait for and free on the MLP's own device, whichever device is current
+  int cur = -1;
+  const bool other =
+      hipGetDevice(&cur) == hipSuccess && cur != h->device && hipSetDevice(h->device) == hipSuccess;
   (void)hipDeviceSynchronize();
   (void)hipFree(h->m.master);
   (void)hipFree(h->m.work);
@@ -369,10 +379,12 @@ void knnj_mlp_free(knnj_mlp* h) {
   (void)hipFree(h->m.m2);
   (void)hipFree(h->m.norm);
   delete h;
+  if (other) (void)hipSetDevice(cur);
 }
 
 knnj_status knnj_mlp_features(const knnj_index* ix, const knnj_csr* R, float* out, void* stream) {
   if (!ix || !R || (!out && R->n_rows > 0)) return fail(KNNJ_EINVAL, "NULL argument");
+  if (const knnj_status rc = check_device(index_device(ix), "the index"); rc != KNNJ_OK) return rc;
   const uint32_t* ll = index_list_len(ix);
   knnj_index_info info;
   knnj_status rc = knnj_index_info_get(ix, &info);
@@ -434,6 +446,7 @@ static knnj_status batch_grad(const Mlp& m, const float* X, const float* y, cons
 knnj_status knnj_mlp_grad(knnj_mlp* h, const float* X, const float* y, int64_t n, float tau, float* grad_out,
                           float* loss_out, void* stream) {
   if (!h || !X || !y || !grad_out || !loss_out || n < 1) return fail(KNNJ_EINVAL, "bad argument");
+  if (const knnj_status rc = check_device(h->device, "the MLP"); rc != KNNJ_OK) return rc;
   if (!(tau > 0.0f && tau < 1.0f)) return fail(KNNJ_EINVAL, "tau must be in (0, 1)");
   hipStream_t st = (hipStream_t)stream;
   Batch b;
@@ -450,6 +463,7 @@ knnj_status knnj_mlp_grad(knnj_mlp* h, const float* X, const float* y, int64_t n
 knnj_status knnj_mlp_train(knnj_mlp* h, const float* X, const float* y, int64_t n, const knnj_train_opts* opt,
                            float* epoch_loss, void* stream) {
   if (!h || !X || !y || n < 1 || !opt) return fail(KNNJ_EINVAL, "bad argument");
+  if (const knnj_status rc = check_device(h->device, "the MLP"); rc != KNNJ_OK) return rc;
   if (opt->epochs < 1 || opt->batch < 1 || opt->batch > 65536 || !(opt->lr > 0.0f) || !(opt->tau > 0.0f) ||
       !(opt->tau < 1.0f))
     return fail(KNNJ_EINVAL, "bad training options");
@@ -504,6 +518,7 @@ knnj_status knnj_mlp_train(knnj_mlp* h, const float* X, const float* y, int64_t 
 
 knnj_status knnj_mlp_predict(const knnj_mlp* h, const float* X, int64_t n, float* theta_out, void* stream) {
   if (!h || (n > 0 && (!X || !theta_out)) || n < 0) return fail(KNNJ_EINVAL, "bad argument");
+  if (const knnj_status rc = check_device(h->device, "the MLP"); rc != KNNJ_OK) return rc;
   if (n == 0) return KNNJ_OK;
   hipStream_t st = (hipStream_t)stream;
   k_mlp_forward<<<unsigned((n + kSB - 1) / kSB), kBlock, kFwdSmem, st>>>(n, X, nullptr, h->m.work, h->m.norm,
@@ -515,6 +530,7 @@ knnj_status knnj_mlp_predict(const knnj_mlp* h, const float* X, int64_t n, float
 
 knnj_status knnj_mlp_get_state(const knnj_mlp* h, float* params, float* norm) {
   if (!h || !params || !norm) return fail(KNNJ_EINVAL, "NULL argument");
+  if (const knnj_status rc = check_device(h->device, "the MLP"); rc != KNNJ_OK) return rc;
   KNNJ_HIP(hipDeviceSynchronize());
   KNNJ_HIP(hipMemcpy(params, h->m.work, sizeof(float) * kParams, hipMemcpyDeviceToHost));
   KNNJ_HIP(hipMemcpy(norm, h->m.norm, sizeof(float) * (2 * kIn + 1), hipMemcpyDeviceToHost));
@@ -523,6 +539,7 @@ knnj_status knnj_mlp_get_state(const knnj_mlp* h, float* params, float* norm) {
 
 knnj_status knnj_mlp_set_state(knnj_mlp* h, const float* params, const float* norm) {
   if (!h || !params || !norm) return fail(KNNJ_EINVAL, "NULL argument");
+  if (const knnj_status rc = check_device(h->device, "the MLP"); rc != KNNJ_OK) return rc;
   std::vector<float> w(kParams);
   for (int i = 0; i < kParams; ++i) w[i] = bf16_round_host(params[i]);
   for (int c = 0; c < kIn; ++c)
