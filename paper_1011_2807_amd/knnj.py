@@ -103,6 +103,20 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _require(t: Optional[torch.Tensor], name: str, dtype: torch.dtype, numel: int, at_least: bool = False):
+    """Check a device array handed to the library: dtype, contiguity, the
+    current device, and size (the kernels write exactly what the sizes say)."""
+    if t is None:
+        return
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if t.device.type != "cuda" or t.device.index != torch.cuda.current_device():
+        raise ValueError("%s must be on the current HIP device" % name)
+    if (t.numel() < numel) if at_least else (t.numel() != numel):
+        raise ValueError("%s has %d elements, %s %d" % (name, t.numel(), "needs at least" if at_least else "needs",
+                                                         numel))
+
+
 @dataclass
 class DeviceCSR:
     """CSR matrix in device memory (torch tensors)."""
@@ -127,11 +141,14 @@ class DeviceCSR:
         return KNNJ_U8 if self.values.dtype == torch.uint8 else KNNJ_F32
 
     def _c(self) -> _CSR:
-        for t, dt in ((self.indptr, torch.int64), (self.indices, torch.int32)):
-            if t.dtype != dt or not t.is_contiguous() or t.device.type != "cuda":
-                raise TypeError("CSR arrays must be contiguous device tensors (indptr int64, indices int32)")
-        if self.values.dtype not in (torch.uint8, torch.float32) or not self.values.is_contiguous():
-            raise TypeError("CSR values must be a contiguous uint8 or float32 device tensor")
+        if self.values.dtype not in (torch.uint8, torch.float32):
+            raise TypeError("CSR values must be a uint8 or float32 device tensor")
+        nnz = int(self.indices.numel())
+        _require(self.indptr, "indptr", torch.int64, self.indptr.numel())
+        _require(self.indices, "indices", torch.int32, nnz)
+        _require(self.values, "values", self.values.dtype, nnz)
+        if self.indptr.dim() != 1 or self.indptr.numel() < 1:
+            raise ValueError("indptr must be a 1-d tensor of n_rows + 1 offsets")
         return _CSR(self.n_rows, self.n_dims, self.dtype, int(self.indices.shape[0]), _ptr(self.indptr),
                     _ptr(self.indices), _ptr(self.values))
 
@@ -193,9 +210,13 @@ def build_index(S: DeviceCSR, tile_width: int = 0, dense_head: int = 0, stream=N
 
 
 def _outputs(n: int, k: int, dtype: int, out):
-    if out is not None:
-        return out
     sdt = torch.int32 if dtype == KNNJ_U8 else torch.float32
+    if out is not None:
+        ids, sc, cnt = out
+        _require(ids, "out ids", torch.int32, n * k)
+        _require(sc, "out scores", sdt, n * k)
+        _require(cnt, "out count", torch.int32, n)
+        return out
     return (torch.empty((n, k), dtype=torch.int32, device="cuda"), torch.empty((n, k), dtype=sdt, device="cuda"),
             torch.empty(n, dtype=torch.int32, device="cuda"))
 
@@ -226,10 +247,9 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     o.r_max_row_nnz = int(r_max_row_nnz)
     o.r_block_rows = int(r_block_rows)
     o.tiles_per_launch = int(tiles_per_launch)
-    if theta_seed is not None:
-        assert theta_seed.dtype == torch.float32 and theta_seed.is_cuda and theta_seed.numel() == R.n_rows
-    if stats is not None:
-        assert stats.dtype == torch.int64 and stats.is_cuda and stats.numel() >= STAT_COUNT
+    _require(theta_seed, "theta_seed", torch.float32, R.n_rows)
+    _require(stats, "stats", torch.int64, STAT_COUNT, at_least=True)
+    _require(fallback_out, "fallback_out", torch.uint8, R.n_rows)
     o.theta_seed = _ptr(theta_seed)
     o.stats = _ptr(stats)
     o.fallback_out = _ptr(fallback_out)
@@ -282,6 +302,13 @@ def _load_mlp(lib):
     return lib
 
 
+def _check_xy(X: torch.Tensor, y: Optional[torch.Tensor] = None):
+    if X.dim() != 2 or X.shape[1] != MLP_FEATURES:
+        raise ValueError("X must be [n, %d]" % MLP_FEATURES)
+    _require(X, "X", torch.float32, X.numel())
+    _require(y, "y", torch.float32, X.shape[0])
+
+
 class Mlp:
     """Threshold-predicting MLP (64-128-128-1, bfloat16 weights) held by the library."""
 
@@ -301,8 +328,7 @@ class Mlp:
 
     def train(self, X: torch.Tensor, y: torch.Tensor, epochs: int = 20, batch: int = 1024, lr: float = 1e-3,
               tau: float = 0.05, seed: int = 0, stream=None):
-        assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous() and X.shape[1] == MLP_FEATURES
-        assert y.dtype == torch.float32 and y.is_cuda and y.numel() == X.shape[0]
+        _check_xy(X, y)
         o = _TrainOpts(int(epochs), int(batch), float(lr), float(tau), int(seed))
         losses = (ctypes.c_float * int(epochs))()
         _check(self._lib.knnj_mlp_train(self._h, _ptr(X), _ptr(y), int(X.shape[0]), ctypes.byref(o), losses,
@@ -310,12 +336,13 @@ class Mlp:
         return list(losses)
 
     def predict(self, X: torch.Tensor, stream=None) -> torch.Tensor:
-        assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous() and X.shape[1] == MLP_FEATURES
+        _check_xy(X)
         out = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
         _check(self._lib.knnj_mlp_predict(self._h, _ptr(X), int(X.shape[0]), _ptr(out), _stream(stream)))
         return out
 
     def grad(self, X: torch.Tensor, y: torch.Tensor, tau: float, stream=None):
+        _check_xy(X, y)
         g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
         _check(self._lib.knnj_mlp_grad(self._h, _ptr(X), _ptr(y), int(X.shape[0]), float(tau), _ptr(g), _ptr(loss),
@@ -331,7 +358,8 @@ class Mlp:
     def set_state(self, params: np.ndarray, norm: np.ndarray):
         p = np.ascontiguousarray(params, dtype=np.float32)
         nrm = np.ascontiguousarray(norm, dtype=np.float32)
-        assert p.shape == (MLP_PARAMS,) and nrm.shape == (MLP_NORM,)
+        if p.shape != (MLP_PARAMS,) or nrm.shape != (MLP_NORM,):
+            raise ValueError("params must be [%d] and norm [%d]" % (MLP_PARAMS, MLP_NORM))
         _check(self._lib.knnj_mlp_set_state(self._h, ctypes.c_void_p(p.ctypes.data), ctypes.c_void_p(nrm.ctypes.data)))
 
     def free(self):

@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import types
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -33,3 +34,27 @@ def test_binding_loads():
     import paper_1011_2807_amd as kj
     lib = kj.load_library()
     assert lib.knnj_last_error() == b""
+
+
+def test_binding_rejects_bad_arrays_before_any_call():
+    """Arrays the kernels would read or write out of bounds are refused on the
+    host: wrong dtype, non-contiguous, host memory, or too few elements."""
+    import pytest
+    import torch
+    import paper_1011_2807_amd as kj
+    from paper_1011_2807_amd import knnj
+    ok = torch.zeros(6, dtype=torch.int32)
+    with pytest.raises(TypeError):
+        knnj._require(ok.to(torch.int64), "x", torch.int32, 6)
+    with pytest.raises(TypeError):
+        knnj._require(torch.zeros(12, dtype=torch.int32)[::2], "x", torch.int32, 6)
+    with pytest.raises(ValueError):          # host tensor: not on the HIP device
+        knnj._require(ok, "x", torch.int32, 6)
+    with pytest.raises(ValueError):
+        kj.knn_join(types.SimpleNamespace(dtype=knnj.KNNJ_U8, _h=None), kj.DeviceCSR(torch.zeros(2, dtype=torch.int64), torch.zeros(1, dtype=torch.int32),
+                                       torch.ones(1, dtype=torch.uint8), 4), 2,
+                    out=(ok, ok, ok))
+    with pytest.raises(TypeError):
+        kj.DeviceCSR(torch.zeros(2, dtype=torch.int64), torch.zeros(1, dtype=torch.int32),
+                     torch.ones(1, dtype=torch.int16), 4)._c()
+    assert knnj._require(None, "x", torch.int32, 6) is None
