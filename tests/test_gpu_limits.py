@@ -53,6 +53,7 @@ def _widest(run, **index_opts):
             ix = kj.build_index(_dev(run.S), tile_width=t, **index_opts)
             got = run(ix)
             torch.cuda.synchronize()
+            print("  widest tile", t, flush=True)
             return t, got
         except kj.KnnjError as e:
             assert e.code == EUNSUPPORTED, (t, e)
