@@ -65,7 +65,29 @@ def _args():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--print-kernel-hash", action="store_true")
+    ap.add_argument("--sweep", choices=sorted(SWEEPS), default=None,
+                    help="run one of the paper's experiment sweeps on synthetic data (one JSON line per point)")
     return ap.parse_args()
+
+
+# The paper's experiment sweeps (Sec. 5) on synthetic stand-ins.  data_size and
+# relative_size use the paper's own synthetic setting (10,000 dimensions; here
+# the small workload's generator: uniform feature ids, nnz U[20,100], uint8
+# values); k uses the sizes of the paper's Yeast (R) and Worm (S) spectra sets
+# with the medium workload's skewed generator in place of the spectra.  k = 5 is
+# the paper's default.  Every point times BF, IIB (list walk and dense head) and
+# IIIB (as printed and refined) on the same queries.
+SWEEPS = {
+    # Fig. 1: data size, |R| = |S| = n
+    "data_size": dict(figure="Fig. 1", gen="tiny",
+                      points=[dict(n_r=n, n_s=n, k=5) for n in (10_000, 20_000, 30_000, 40_000, 50_000)]),
+    # Fig. 2: relative size, |R| = 10,000 and |S| from 1,000 to 100,000 (R:S from 10:1 to 1:10)
+    "relative_size": dict(figure="Fig. 2", gen="tiny",
+                          points=[dict(n_r=10_000, n_s=n, k=5)
+                                  for n in (1_000, 2_000, 5_000, 10_000, 20_000, 50_000, 100_000)]),
+    # Fig. 3: k from 5 to 20, |R| = 35,236 and |S| = 207,804
+    "k": dict(figure="Fig. 3", gen="medium", points=[dict(n_r=35_236, n_s=207_804, k=k) for k in (5, 10, 15, 20)]),
+}
 
 
 KERNEL_SOURCES = ("common.hpp", "select.hpp", "walk.hpp", "join.hip", "head.hip")
@@ -108,6 +130,43 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_baseline_leg(R, S, k, gpu_out, n_check, cpu_seconds, f32):
+    """The cpu_baseline leg, the only place this script runs the oracle: the
+    oracle as it stands (one thread) on random queries of the workload, against
+    all of S, outside the timed region.  Its first n_check rows double as a
+    spot check of the GPU result gpu_out (ids, scores, counts; u8 bit-exact,
+    f32 counts equal and scores within 1e-5 relative); when cpu_seconds > 0 a
+    further sample sized to about that much CPU time follows.  The rate over
+    every row it ran is the reported baseline.  Returns (check, baseline)."""
+    import oracle
+    n_r = R.n_rows
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(n_r, size=max(1, min(n_check, n_r)), replace=False))
+    ids, sc, cnt = [x.cpu().numpy() for x in gpu_out]
+    t0 = time.time()
+    w_ids, w_sc, w_cnt = oracle.bf_topk_rows(R, S, k, rows)
+    el = time.time() - t0
+    if not f32:
+        ok = bool(np.array_equal(ids[rows], w_ids) and np.array_equal(cnt[rows], w_cnt) and
+                  np.array_equal(sc[rows].astype(np.int64), w_sc))
+    else:
+        # float scores within 1e-5 of the fp64 oracle; ids may differ only on near-ties
+        ok = bool(np.array_equal(cnt[rows], w_cnt) and np.allclose(sc[rows], w_sc, rtol=1e-5, atol=0))
+    n_done = len(rows)
+    if cpu_seconds > 0:
+        per_q = el / n_done
+        n_more = int(max(1, min(n_r, cpu_seconds / max(per_q, 1e-6))))
+        more = rng.choice(n_r, size=n_more, replace=False)
+        t1 = time.time()
+        oracle.bf_topk_rows(R, S, k, more)
+        el += time.time() - t1
+        n_done += n_more
+    cpu = {"value": round(n_done / el, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
+           "sample": "%d random queries of the same workload against all of S, one thread, %.1fs"
+                     " (the first %d also check the GPU result)" % (n_done, el, len(rows))}
+    return {"queries": len(rows), "exact": ok}, cpu
+
+
 def main():
     a = _args()
     if a.print_kernel_hash:
@@ -130,6 +189,8 @@ def main():
     import synth
     import paper_1011_2807_amd as kj
 
+    if a.sweep:
+        return run_sweep(a)
     if a.workload == "batched":
         return run_batched(a)
     wl = synth.WORKLOADS[a.workload]
@@ -320,31 +381,9 @@ def main():
         iiib["learned_vs_refined_speedup"] = round(iiib["refined"]["ms"] / res["ms"], 3)
         iiib["learned_vs_plain_speedup"] = round(iiib["plain"]["ms"] / res["ms"], 3)
 
-    # spot check against the oracle (not timed)
-    import oracle
-    ids, sc, cnt = [x.cpu().numpy() for x in out]
-    rng = np.random.default_rng(0)
-    rows = rng.choice(n_r, size=min(a.check, n_r), replace=False)
-    tc = time.time()
-    w_ids, w_sc, w_cnt = oracle.bf_topk_rows(R, S, k, rows)
-    t_check = time.time() - tc
-    if sdt == torch.int32:
-        ok = bool(np.array_equal(ids[rows], w_ids) and np.array_equal(cnt[rows], w_cnt) and
-                  np.array_equal(sc[rows].astype(np.int64), w_sc))
-    else:
-        # float scores within 1e-5 of the fp64 oracle; ids may differ only on near-ties
-        ok = bool(np.array_equal(cnt[rows], w_cnt) and np.allclose(sc[rows], w_sc, rtol=1e-5, atol=0))
-    cpu = None
-    if not a.no_cpu:
-        # the oracle as it stands, one thread, on a bounded sample sized from the check's speed
-        per_q = t_check / max(1, len(rows))
-        n_cpu = int(max(1, min(n_r, a.cpu_seconds / max(per_q, 1e-6))))
-        rows_cpu = rng.choice(n_r, size=n_cpu, replace=False)
-        t1 = time.time()
-        oracle.bf_topk_rows(R, S, k, rows_cpu)
-        el = time.time() - t1
-        cpu = {"value": round(n_cpu / el, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
-               "sample": "%d random queries of the same workload against all of S, one thread, %.1fs" % (n_cpu, el)}
+    check, cpu = cpu_baseline_leg(R, S, k, out, a.check, 0.0 if a.no_cpu else a.cpu_seconds,
+                                  f32=sdt != torch.int32)
+    ok = check["exact"]
     res = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
@@ -355,12 +394,82 @@ def main():
                    "tile_width": ix.tile_width, "nnz_s": S.nnz, "nnz_r": R.nnz},
         "postings_entries_per_s": eps, "postings_GBps": round(gbps, 1), "postings_entries_per_step": walked,
         "walked_entries_per_step": walked_tail, "iib_plain_walk": walk,
-        "index_build_s": round(t_build, 3), "oracle_spot_check": {"queries": len(rows), "exact": ok},
+        "index_build_s": round(t_build, 3), "oracle_spot_check": check,
         "iiib": iiib, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))
     bad = not ok or (iiib is not None and not all(iiib[v]["identical_to_iib"] for v in ("plain", "refined", "learned")))
     bad = bad or (walk is not None and not walk["identical_to_dense_head"])
+    if bad:
+        sys.exit(1)
+
+
+def run_sweep(a):
+    """One JSON line per point of a sweep: milliseconds per full join for each
+    algorithm (mean of 3 timed runs after one untimed run, HIP events), every
+    output identical to IIB's, and the oracle's rows (cpu_baseline leg)."""
+    import torch
+    import synth
+    import paper_1011_2807_amd as kj
+    sw = SWEEPS[a.sweep]
+    gen = sw["gen"]
+    perm = synth.workload_perm(gen)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    bad = False
+    for pt in sw["points"]:
+        n_r, n_s, k = pt["n_r"], pt["n_s"], pt["k"]
+        S = synth.make(gen, "S", n_rows=n_s, perm=perm)
+        R = synth.make(gen, "R", n_rows=n_r, perm=perm)
+        dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+        ix = kj.build_index(dS, tile_width=4096)
+        ixh = kj.build_index(dS, tile_width=2048, dense_head=128)
+        torch.cuda.synchronize()
+
+        def outs():
+            return (torch.empty((n_r, k), dtype=torch.int32, device="cuda"),
+                    torch.empty((n_r, k), dtype=torch.int32, device="cuda"),
+                    torch.empty(n_r, dtype=torch.int32, device="cuda"))
+
+        runs = {
+            "bf": lambda o: kj.knn_join_bf(dS, dR, k, out=o),
+            "iib": lambda o: kj.knn_join(ix, dR, k, out=o, validate=False),
+            "iib_dense_head": lambda o: kj.knn_join(ixh, dR, k, out=o, validate=False),
+            "iiib": lambda o: kj.knn_join(ix, dR, k, algo="iiib", out=o, validate=False),
+            "iiib_refined": lambda o: kj.knn_join(ix, dR, k, algo="iiib", bound_filter=True, level_drop=8, out=o,
+                                                  validate=False),
+        }
+        ms, res = {}, {}
+        for name, fn in runs.items():
+            o = outs()
+            reps = 0
+            while True:
+                # the first run is untimed unless it alone takes over 2 s
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(max(1, reps)):
+                    fn(o)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1)
+                if reps or t > 2000.0:
+                    ms[name] = round(t / max(1, reps), 3)
+                    break
+                reps = 3
+            res[name] = o
+        same = {name: all(torch.equal(x, y) for x, y in zip(o, res["iib"])) for name, o in res.items()}
+        check, cpu = cpu_baseline_leg(R, S, k, res["iib"], 2, 0.0, f32=False)
+        bad |= not check["exact"] or not all(same.values())
+        print(json.dumps({
+            "sweep": a.sweep, "figure": sw["figure"], "data": "synthetic", "generator": gen,
+            "n_r": n_r, "n_s": n_s, "d": synth.WORKLOADS[gen]["d"], "k": k, "nnz_r": R.nnz, "nnz_s": S.nnz,
+            "ms_per_join": ms, "queries_per_s": {x: round(n_r / (v / 1e3), 1) for x, v in ms.items()},
+            "identical_to_iib": same, "oracle_spot_check": check, "cpu_baseline": cpu,
+            "notes": "mean of 3 timed joins after one untimed (one timed join where it takes over 2 s); bf includes "
+                     "its input validation (a device check of R and S, one synchronisation); iib: T = 4096; "
+                     "iib_dense_head: T = 2048, dense head 128; iiib_refined: bound filter, level drop 8",
+        }), flush=True)
+        del ix, ixh
     if bad:
         sys.exit(1)
 
@@ -436,13 +545,8 @@ def run_batched(a):
     _log("graph (IIIB k=1 + k=10): %.1f ms" % ms_graph)
     same10 = all(torch.equal(x, y) for x, y in zip(o10, ref))
     k1_prefix = bool(torch.equal(o1[0][:, 0], o10[0][:, 0]) and torch.equal(o1[1][:, 0], o10[1][:, 0]))
-    import oracle
-    rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(n_r, size=min(a.check, n_r), replace=False))
-    w = oracle.bf_topk_rows(R, S, 10, rows)
-    g_ids, g_sc, g_cnt = [x.cpu().numpy() for x in ref]
-    ok = bool(np.array_equal(g_ids[rows], w[0]) and np.array_equal(g_sc[rows].astype(np.int64), w[1]) and
-              np.array_equal(g_cnt[rows], w[2]))
+    check, cpu = cpu_baseline_leg(R, S, 10, ref, a.check, 0.0, f32=False)
+    ok = check["exact"]
     qps = n_r / (ms_iib / 1e3)
     entry_bytes = 4
     head = tune_iib["dense_head"]
@@ -460,12 +564,12 @@ def run_batched(a):
                               "k10_identical_to_iib": same10, "k1_is_first_column_of_k10": k1_prefix,
                               "level_drop": tune_iiib["level_drop"]},
         "autotune": {"iib": tune_iib["timings"], "iiib": tune_iiib["timings"]},
-        "oracle_spot_check": {"queries": len(rows), "exact": ok},
+        "oracle_spot_check": check,
         "roofline": {"kernel": "k_iibh_tiles" if head else "k_iib_tile", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                      "avg_launch_ms": round(ms_iib / launches, 4), "launches_per_step": launches},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(res))
     if not (ok and same10 and k1_prefix):

@@ -124,7 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_iib_persistent(Sched sch, int32_t ti
 }
 
 // Brute force (Algorithm 2): scores of rows [s0, s0 + T) of S by a two-pointer
-// merge of r (staged in local memory) with each s; one thread per s.
+// merge of r (staged in local memory) with each s; one thread per s.  The sum
+// runs in the score map type of the tile kernels (fp64 for float32 data, where
+// each product is exact) and is stored rounded to the output type.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_bf(int32_t log2_tile, int64_t n_s, int32_t k, int64_t q0,
                                                const int64_t* __restrict__ r_ptr, const int32_t* __restrict__ r_idx,
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_bf(int32_t log2_tile, int64_t n_s, i
                                                typename ScoreOf<V>::T* __restrict__ out_sc,
                                                int32_t* __restrict__ out_cnt) {
   using S = typename ScoreOf<V>::T;
+  using A = typename AccOf<V>::T;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint32_t tmp[kBlock / kWave + 1];
   __shared__ int32_t rd[kMaxRowNnz];
@@ -154,13 +157,13 @@ __global__ __launch_bounds__(kBlock) void k_bf(int32_t log2_tile, int64_t n_s, i
     const int n_valid = int(n_s - s0 < T ? n_s - s0 : T);
     for (int i = threadIdx.x; i < n_valid; i += kBlock) {
       const int64_t sb = s_ptr[s0 + i], se = s_ptr[s0 + i + 1];
-      S ret = S(0);
+      A ret = A(0);
       int a = 0;
       int64_t b = sb;
       while (a < nr && b < se) {
         const int32_t dr = rd[a], ds = s_idx[b];
         if (dr == ds) {
-          ret += rw[a] * S(s_val[b]);
+          ret += A(rw[a]) * A(s_val[b]);
           ++a;
           ++b;
         } else if (dr > ds) {
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_bf(int32_t log2_tile, int64_t n_s, i
           ++a;
         }
       }
-      acc[i] = ret;
+      acc[i] = S(ret);
     }
     __syncthreads();
     tile_select<S, false>(acc, n_valid, s0, k, out_ids + q * k, out_sc + q * k, out_cnt + q, sm);
