@@ -87,6 +87,11 @@ SWEEPS = {
                                   for n in (1_000, 2_000, 5_000, 10_000, 20_000, 50_000, 100_000)]),
     # Fig. 3: k from 5 to 20, |R| = 35,236 and |S| = 207,804
     "k": dict(figure="Fig. 3", gen="medium", points=[dict(n_r=35_236, n_s=207_804, k=k) for k in (5, 10, 15, 20)]),
+    # Fig. 4: buffer size.  The medium workload with S left in host memory and
+    # read in blocks of 10% to 50% of its rows (the blocked join), beside the
+    # join of an index of all of S in device memory
+    "buffer": dict(figure="Fig. 4", gen="medium",
+                   points=[dict(n_r=100_000, n_s=1_000_000, k=10, block_frac=f) for f in (0.1, 0.2, 0.3, 0.5)]),
 }
 
 
@@ -416,6 +421,8 @@ def run_sweep(a):
     perm = synth.workload_perm(gen)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.sweep == "buffer":
+        return run_buffer_sweep(a, sw, perm, stream)
     bad = False
     for pt in sw["points"]:
         n_r, n_s, k = pt["n_r"], pt["n_s"], pt["k"]
@@ -470,6 +477,60 @@ def run_sweep(a):
                      "iib_dense_head: T = 2048, dense head 128; iiib_refined: bound filter, level drop 8",
         }), flush=True)
         del ix, ixh
+    if bad:
+        sys.exit(1)
+
+
+def run_buffer_sweep(a, sw, perm, stream):
+    """Fig. 4's buffer sweep: the blocked join (S in page-locked host memory,
+    copied block by block on a stream of its own while the previous block is
+    joined) at each block size, against the join of one index of all of S in
+    device memory; IIB with the dense head (128, T = 2048), k = 10.  One JSON
+    line per block size, phase times from the library (copy = I/O)."""
+    import torch
+    import synth
+    import paper_1011_2807_amd as kj
+    pt0 = sw["points"][0]
+    n_r, n_s, k = pt0["n_r"], pt0["n_s"], pt0["k"]
+    gen_name = sw["gen"]
+    S = synth.make(gen_name, "S", n_rows=n_s, perm=perm)
+    R = synth.make(gen_name, "R", n_rows=n_r, perm=perm)
+    hS = kj.HostCSR(S)
+    dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+    t0 = time.time()
+    ix = kj.build_index(dS, tile_width=2048, dense_head=128)
+    torch.cuda.synchronize()
+    t_build = (time.time() - t0) * 1e3
+    ref = kj.knn_join(ix, dR, k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    kj.knn_join(ix, dR, k, validate=False, out=ref)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_in = e0.elapsed_time(e1)
+    del ix, dS
+    s_bytes = int(S.indptr.nbytes + S.indices.nbytes + S.values.nbytes)
+    check, cpu = cpu_baseline_leg(R, S, k, ref, 2, 0.0, f32=False)
+    bad = not check["exact"]
+    for pt in sw["points"]:
+        block_rows = int(round(pt["block_frac"] * n_s))
+        kj.knn_join_blocked(hS, dR, k, block_rows, tile_width=2048, dense_head=128)  # untimed
+        ids, sc, cnt, t = kj.knn_join_blocked(hS, dR, k, block_rows, tile_width=2048, dense_head=128)
+        same = all(torch.equal(x, y) for x, y in zip((ids, sc, cnt), ref))
+        bad |= not same
+        print(json.dumps({
+            "sweep": "buffer", "figure": sw["figure"], "data": "synthetic", "generator": gen_name,
+            "n_r": n_r, "n_s": n_s, "d": synth.WORKLOADS[gen_name]["d"], "k": k, "block_rows": block_rows,
+            "block_share_of_S": pt["block_frac"], "n_blocks": t["n_blocks"],
+            "phase_ms": {x: round(t[x], 3) for x in ("copy_ms", "build_ms", "join_ms", "merge_ms", "total_ms")},
+            "queries_per_s": round(n_r / (t["total_ms"] / 1e3), 1),
+            "copy_GBps": round(s_bytes / (t["copy_ms"] / 1e3) / 1e9, 2) if t["copy_ms"] > 0 else None,
+            "in_memory": {"join_ms": round(ms_in, 3), "index_build_ms": round(t_build, 1),
+                          "queries_per_s": round(n_r / (ms_in / 1e3), 1)},
+            "identical_to_in_memory": same, "oracle_spot_check": check, "cpu_baseline": cpu,
+            "notes": "IIB with dense head 128, T = 2048; one untimed blocked run first; S bytes %d" % s_bytes,
+        }), flush=True)
     if bad:
         sys.exit(1)
 

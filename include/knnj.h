@@ -212,6 +212,41 @@ knnj_status knnj_join(const knnj_index* ix, const knnj_csr* R, int32_t k, const 
 knnj_status knnj_join_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* out_ids, void* out_scores,
                          int32_t* out_count, void* stream);
 
+/* Phase times of knnj_join_blocked in milliseconds (host struct, filled when
+ * the call returns).  Copies run on a stream of their own and overlap the
+ * previous block's join, so the phases may add up to more than total_ms. */
+typedef struct {
+  int64_t n_blocks;
+  double copy_ms;  /* host-to-device transfer of the S blocks (I/O) */
+  double build_ms; /* per-block index builds, including their validation */
+  double join_ms;  /* joins of R with each block */
+  double merge_ms; /* merges of each block's k best into the running result */
+  double total_ms;
+} knnj_block_stats;
+
+/*
+ * Block nested loop with S in host memory (Algorithm 1, whose outer loop reads
+ * S block by block into a buffer; Sec. 5 measures its I/O): S is taken in
+ * blocks of block_rows rows in ascending row order.  Each block is copied to
+ * the device (while the previous block is joined), indexed as by
+ * knnj_build_index with index_opts, and joined with R as by knnj_join with
+ * join_opts; its k best per query (row ids offset by the block's first row)
+ * are then merged into the running result under the same order (score desc,
+ * id asc).  The result equals knnj_join on an index of all of S.
+ * S: CSR in host memory (indptr, indices, values host pointers; page-locked
+ * memory lets the copies run asynchronously); R and the outputs: device, as
+ * for knnj_join, except that out_count must not be NULL.  join_opts->theta_seed must be NULL (a seed bounds the k-th
+ * score over all of S, not over a block).  Device memory in use: about two
+ * blocks of S, one block's index and one block's results.  Synchronises the
+ * stream before it returns; block_stats (nullable, host) receives the phase
+ * times.
+ * Errors: as knnj_build_index and knnj_join; EINVAL for block_rows < 1 or a
+ * seed.
+ */
+knnj_status knnj_join_blocked(const knnj_csr* S_host, int64_t block_rows, const knnj_index_opts* index_opts,
+                              const knnj_csr* R, int32_t k, const knnj_join_opts* join_opts, int32_t* out_ids,
+                              void* out_scores, int32_t* out_count, knnj_block_stats* block_stats, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned threshold seed (not in the paper; its Sec. 6 asks for stronger
  * refinement).  A 64-128-128-1 MLP (ReLU, bfloat16 weights, float32

@@ -51,6 +51,11 @@ class _JoinOpts(ctypes.Structure):
                 ("tiles_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
+class _BlockStats(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int64), ("copy_ms", ctypes.c_double), ("build_ms", ctypes.c_double),
+                ("join_ms", ctypes.c_double), ("merge_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 class _IndexInfo(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_dims", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("tile_width", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
@@ -81,9 +86,11 @@ def load_library(path: str = LIB_PATH):
     lib.knnj_join.restype = I32
     lib.knnj_join_bf.argtypes = [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), I32, P, P, P, P]
     lib.knnj_join_bf.restype = I32
+    lib.knnj_join_blocked.argtypes = [ctypes.POINTER(_CSR), I64, ctypes.POINTER(_IndexOpts), ctypes.POINTER(_CSR),
+                                      I32, ctypes.POINTER(_JoinOpts), P, P, P, ctypes.POINTER(_BlockStats), P]
+    lib.knnj_join_blocked.restype = I32
     lib.knnj_last_error.argtypes = []
     lib.knnj_last_error.restype = ctypes.c_char_p
-    del I64
     _lib = lib
     return lib
 
@@ -257,6 +264,60 @@ def knn_join(index: Index, R: DeviceCSR, k: int, algo: str = "iib", r_block_rows
     _check(lib.knnj_join(index._h, ctypes.byref(c), int(k), ctypes.byref(o), _ptr(ids), _ptr(sc), _ptr(cnt),
                          _stream(stream)))
     return ids, sc, cnt
+
+
+class HostCSR:
+    """CSR matrix in host memory for the blocked join.  pin=True copies it into
+    page-locked memory (torch pin_memory), so block copies run asynchronously."""
+
+    def __init__(self, m, pin: bool = True):
+        arrs = []
+        for a, dt in ((m.indptr, torch.int64), (m.indices, torch.int32), (m.values, None)):
+            t = torch.as_tensor(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a
+            if t.device.type != "cpu" or not t.is_contiguous() or (dt is not None and t.dtype != dt):
+                raise TypeError("HostCSR arrays must be contiguous host arrays (indptr int64, indices int32)")
+            arrs.append(t.pin_memory() if pin and not t.is_pinned() else t)
+        self.indptr, self.indices, self.values = arrs
+        if self.values.dtype not in (torch.uint8, torch.float32):
+            raise TypeError("HostCSR values must be uint8 or float32")
+        if self.indices.numel() != self.values.numel() or self.indptr.dim() != 1 or self.indptr.numel() < 1:
+            raise ValueError("HostCSR: indptr must be 1-d with n_rows + 1 entries; indices and values of one size")
+        self.n_dims = int(m.n_dims)
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.indptr.numel()) - 1
+
+    def _c(self) -> _CSR:
+        return _CSR(self.n_rows, self.n_dims, KNNJ_U8 if self.values.dtype == torch.uint8 else KNNJ_F32,
+                    int(self.indices.numel()), _ptr(self.indptr), _ptr(self.indices), _ptr(self.values))
+
+
+def knn_join_blocked(S: HostCSR, R: DeviceCSR, k: int, block_rows: int, tile_width: int = 0, dense_head: int = 0,
+                     algo: str = "iib", bound_filter: bool = False, level_drop: int = 0, validate: bool = True,
+                     stats: Optional[torch.Tensor] = None, out=None, stream=None):
+    """Block nested loop with S in host memory (see knnj.h): S is copied to the
+    device block_rows rows at a time, each block indexed (tile_width,
+    dense_head) and joined; the result equals knn_join on all of S.
+    Returns (ids, scores, count, phase times in ms)."""
+    lib = load_library()
+    if not isinstance(S, HostCSR):
+        raise TypeError("S must be a HostCSR")
+    ids, sc, cnt = _outputs(R.n_rows, k, KNNJ_U8 if S.values.dtype == torch.uint8 else KNNJ_F32, out)
+    _require(stats, "stats", torch.int64, STAT_COUNT, at_least=True)
+    io = _IndexOpts(int(tile_width), int(dense_head))
+    o = _JoinOpts()
+    o.algo = KNNJ_IIIB if algo == "iiib" else KNNJ_IIB
+    o.flags = (0 if validate else KNNJ_FLAG_NO_VALIDATE) | (KNNJ_FLAG_IIIB_BOUND if bound_filter else 0)
+    o.level_drop = int(level_drop)
+    o.stats = _ptr(stats)
+    bs = _BlockStats()
+    cs, cr = S._c(), R._c()
+    _check(lib.knnj_join_blocked(ctypes.byref(cs), int(block_rows), ctypes.byref(io), ctypes.byref(cr), int(k),
+                                 ctypes.byref(o), _ptr(ids), _ptr(sc), _ptr(cnt), ctypes.byref(bs), _stream(stream)))
+    times = {f: getattr(bs, f) for f, _ in _BlockStats._fields_}
+    times["n_blocks"] = int(times["n_blocks"])
+    return ids, sc, cnt, times
 
 
 def knn_join_bf(S: DeviceCSR, R: DeviceCSR, k: int, out=None, stream=None):
