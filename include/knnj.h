@@ -230,9 +230,11 @@ typedef struct {
  * blocks of block_rows rows in ascending row order.  Each block is copied to
  * the device (while the previous block is joined), indexed as by
  * knnj_build_index with index_opts, and joined with R as by knnj_join with
- * join_opts; its k best per query (row ids offset by the block's first row)
- * are then merged into the running result under the same order (score desc,
- * id asc).  The result equals knnj_join on an index of all of S.
+ * join_opts, each query starting from its running k-th score (pruneScore
+ * carried across blocks, as Algorithm 1 carries it across S blocks); the rows
+ * a block adds (ids offset by its first row) are then merged into the running
+ * result under the same order (score desc, id asc).  The result equals
+ * knnj_join on an index of all of S.
  * S: CSR in host memory (indptr, indices, values host pointers; page-locked
  * memory lets the copies run asynchronously); R and the outputs: device, as
  * for knnj_join, except that out_count must not be NULL.  join_opts->theta_seed must be NULL (a seed bounds the k-th

@@ -329,9 +329,15 @@ knnj_status reset_sched(Index* ix, int bank, hipStream_t st) {
   return launch_fill_u32(ix->js_heads + size_t(bank) * ix->n_tiles, ix->n_tiles, 0u, st);
 }
 
-knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids,
-                      void* sc, int32_t* cnt, void* stream) {
-  g_last_error.clear();
+}  // extern "C"
+
+namespace knnj {
+
+// knnj_join, and the blocked join's per-block join: with init_out false the
+// outputs already hold each query's list (ids below this index's rows) and the
+// join merges into it, starting from its k-th score.
+knnj_status join_impl(const knnj_index* h, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids,
+                      void* sc, int32_t* cnt, void* stream, bool init_out) {
   if (!h) return fail(KNNJ_EINVAL, "index is NULL");
   Index* ix = impl(h);
   knnj_status rc = check_device(ix->device, "the index");
@@ -351,8 +357,9 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
   }
   if ((rc = overflow_check(ix->dtype, max_r, ix->max_row_nnz)) != KNNJ_OK) return rc;
   if (R->n_rows == 0) return KNNJ_OK;
+  if (!init_out && !cnt) return fail(KNNJ_EINVAL, "a continued join needs out_count");
   if (!cnt && !(cnt = scratch_count(R->n_rows))) return fail(KNNJ_ENOMEM, "count buffer allocation failed");
-  if ((rc = launch_init_out(R->n_rows, k, ids, sc, cnt, st)) != KNNJ_OK) return rc;
+  if (init_out && (rc = launch_init_out(R->n_rows, k, ids, sc, cnt, st)) != KNNJ_OK) return rc;
   uint64_t* slots = nullptr;
   if (o.stats) {
     slots = ix->stat_slots;
@@ -382,6 +389,16 @@ knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const k
   if (rc != KNNJ_OK) return rc;
   if (o.stats && (rc = launch_reduce_stats(slots, o.stats, st)) != KNNJ_OK) return rc;
   return KNNJ_OK;
+}
+
+}  // namespace knnj
+
+extern "C" {
+
+knnj_status knnj_join(const knnj_index* h, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids,
+                      void* sc, int32_t* cnt, void* stream) {
+  g_last_error.clear();
+  return join_impl(h, R, k, opt, ids, sc, cnt, stream, true);
 }
 
 knnj_status knnj_join_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,

@@ -1,7 +1,8 @@
 // Block nested loop with S in host memory (Algorithm 1's outer loop over S
-// blocks): each block is copied to the device on a stream of its own while the
-// previous block is joined, indexed, joined with R, and its k best per query
-// are merged into the running result.
+// blocks, pruneScore carried from block to block): each block is copied to the
+// device on a stream of its own while the previous block is joined, indexed,
+// joined with R starting from every query's running k-th score, and the rows
+// it adds are merged into the running result.
 #include <string.h>
 
 #include <chrono>
@@ -13,11 +14,32 @@ namespace knnj {
 
 knnj_status launch_init_out(int64_t n_rows, int32_t k, int32_t* ids, void* sc, int32_t* cnt, hipStream_t st);
 knnj_status validate_csr(const knnj_csr* m, int32_t* dev_err, hipStream_t st, int32_t* max_row);
+knnj_status join_impl(const knnj_index* h, const knnj_csr* R, int32_t k, const knnj_join_opts* opt, int32_t* ids,
+                      void* sc, int32_t* cnt, void* stream, bool init_out);
 
 // Rows of a block's indptr slice made relative to the block's first entry.
 __global__ void k_rebase(int64_t n, int64_t base, int64_t* __restrict__ p) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     p[i] -= base;
+}
+
+// Start query q's block list from its running k-th score: a query that holds k
+// neighbours gets k placeholders (id -1) at that score, so the block's join
+// admits only rows scoring above it (a row of a later block that ties it ranks
+// after it, as its id is larger) and prunes from the first tile on; any other
+// query starts empty.
+template <typename S>
+__global__ void k_seed_block(int64_t n_q, int32_t k, const S* __restrict__ sc, const int32_t* __restrict__ cnt,
+                             int32_t* __restrict__ b_ids, S* __restrict__ b_sc, int32_t* __restrict__ b_cnt) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n_q) return;
+  const bool full = cnt[q] == k;
+  const S th = full ? sc[q * k + k - 1] : S(0);
+  for (int i = 0; i < k; ++i) {
+    b_ids[q * k + i] = -1;
+    b_sc[q * k + i] = th;
+  }
+  b_cnt[q] = full ? k : 0;
 }
 
 // Merge query q's block result (b_*, ids relative to the block, all above every
@@ -31,9 +53,13 @@ __global__ void k_merge_topk(int64_t n_q, int32_t k, int64_t id_off, const int32
                              S* __restrict__ sc, int32_t* __restrict__ cnt) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= n_q) return;
-  const int na = cnt[q], nb = b_cnt[q];
-  if (nb == 0) return;
   const int32_t* bi = b_ids + q * k;
+  // the block's own rows come first; placeholders (id -1) follow
+  const int nbl = b_cnt[q];
+  int nb = 0;
+  while (nb < nbl && bi[nb] >= 0) ++nb;
+  const int na = cnt[q];
+  if (nb == 0) return;
   const S* bs = b_sc + q * k;
   int32_t* ai = ids + q * k;
   S* as = sc + q * k;
@@ -253,7 +279,14 @@ extern "C" knnj_status knnj_join_blocked(const knnj_csr* S, int64_t block_rows, 
     // by the build two blocks back, which has returned)
     if (b + 1 < n_blocks && (rc = issue_copy(b + 1)) != KNNJ_OK) return rc;
     KNNJ_HIP(hipEventRecord(run.j0, st));
-    rc = knnj_join(ix, R, k, &jo, run.b_ids, run.b_sc, run.b_cnt, st);
+    if (S->dtype == KNNJ_U8)
+      k_seed_block<uint32_t><<<merge_grid, kBlock, 0, st>>>(n_r, k, (const uint32_t*)out_scores, out_count,
+                                                             run.b_ids, (uint32_t*)run.b_sc, run.b_cnt);
+    else
+      k_seed_block<float><<<merge_grid, kBlock, 0, st>>>(n_r, k, (const float*)out_scores, out_count, run.b_ids,
+                                                          (float*)run.b_sc, run.b_cnt);
+    KNNJ_HIP(hipGetLastError());
+    rc = join_impl(ix, R, k, &jo, run.b_ids, run.b_sc, run.b_cnt, st, false);
     if (rc != KNNJ_OK) return rc;
     KNNJ_HIP(hipEventRecord(run.j1, st));
     if (S->dtype == KNNJ_U8)
