@@ -57,7 +57,7 @@ def _args():
     ap.add_argument("--no-iiib", action="store_true", help="skip the IIIB / learned-seed legs")
     ap.add_argument("--persistent", action="store_true", help="IIB: persistent per-tile launches with a work queue")
     ap.add_argument("--dense-head", type=int, default=-1,
-                    help="dimensions kept as dense per-tile blocks (u8 only; -1 = 128 for u8, 0 = plain walk)")
+                    help="dimensions kept as dense per-tile blocks (-1 = 128 for u8, none for f32; 0 = plain walk)")
     ap.add_argument("--tiles-per-launch", type=int, default=4, help="dense-head join: S tiles per launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -283,8 +283,13 @@ def main():
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1)
         walk = {"queries_per_s": round(n_r / (t / 1e3), 1), "ms": round(t, 2), "tile_width": ix.tile_width,
-                "identical_to_dense_head": all(torch.equal(x, y) for x, y in zip(o2, out)),
                 "speedup_of_dense_head": round(t / ms, 3)}
+        if sdt == torch.int32:
+            walk["identical_to_dense_head"] = all(torch.equal(x, y) for x, y in zip(o2, out))
+        else:
+            # float sums in another order: counts equal, scores within the 1e-5 rule
+            walk["counts_equal"] = bool(torch.equal(o2[2], out[2]))
+            walk["max_rel_score_diff"] = float(((o2[1] - out[1]).abs() / out[1].abs().clamp_min(1e-30)).max())
         _log("plain walk", json.dumps(walk))
         del o2
     eps = walked / (ms / 1e3)
@@ -318,7 +323,7 @@ def main():
                         "frac": round(vi / VALU_ISSUE_PEAK, 4)}
     if head:
         # bytes of dense head blocks read per launch (the four queries of a workgroup share each read)
-        hb = -(-n_r // 4) * ix.tile_width * head * min(G, ix.n_tiles)
+        hb = -(-n_r // 4) * ix.tile_width * head * min(G, ix.n_tiles) * (1 if sdt == torch.int32 else 4)
         roof["head_block_bytes_per_launch"] = hb
         roof["head_block_GBps"] = round(hb / (avg_launch_ms / 1e3) / 1e9, 1)
 

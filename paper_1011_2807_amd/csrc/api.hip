@@ -32,7 +32,7 @@ knnj_status launch_lpt_order(int64_t n, const int64_t* r_ptr, const int32_t* r_i
 knnj_status build_head(Index* ix, hipStream_t st);
 knnj_status launch_iib_head(Index* ix, const knnj_csr* R, int32_t k, const int32_t* order, int32_t tiles_per_launch,
                             int32_t* ids, void* sc, int32_t* cnt, uint64_t* slots, hipStream_t st);
-size_t head_smem_bytes(int tile, int k, int H);
+size_t head_smem_bytes(int tile, int k, int H, int dtype);
 knnj_status launch_bf(const knnj_csr* S, const knnj_csr* R, int32_t k, int32_t* ids, void* sc, int32_t* cnt,
                       hipStream_t st);
 size_t tile_smem_bytes(int tile, int k, size_t acc_b);
@@ -139,9 +139,8 @@ knnj_status knnj_build_index(const knnj_csr* S, const knnj_index_opts* opt, void
                                        std::to_string(max_smem) + " bytes per workgroup)");
   const int head = opt ? opt->dense_head : 0;
   if (head != 0) {
-    if (S->dtype != KNNJ_U8) return fail(KNNJ_EUNSUPPORTED, "dense_head needs uint8 data");
     if (head < 64 || head > 256 || (head % 64)) return fail(KNNJ_EINVAL, "dense_head must be 64, 128, 192 or 256");
-    if (head_smem_bytes(tile, 1, head) > size_t(max_smem))
+    if (head_smem_bytes(tile, 1, head, S->dtype) > size_t(max_smem))
       return fail(KNNJ_EUNSUPPORTED, "tile_width too large for the dense-head join's local memory");
   }
   Index* ix = new Index();
@@ -377,7 +376,7 @@ knnj_status join_impl(const knnj_index* h, const knnj_csr* R, int32_t k, const k
       rc = launch_iib_persistent(ix, R, k, make_sched(ix, R->n_rows, ix->js_order, nullptr, 0), ids, sc, cnt, slots,
                                  st);
     } else if (ix->head_h > 0 && !(o.flags & KNNJ_FLAG_NO_DENSE_HEAD) &&
-               head_smem_bytes(ix->tile, k, ix->head_h) <= size_t(device_max_smem(ix->device))) {
+               head_smem_bytes(ix->tile, k, ix->head_h, ix->dtype) <= size_t(device_max_smem(ix->device))) {
       // (a k too large for the dense-head kernel's local memory takes the plain walk)
       rc = launch_iib_head(ix, R, k, ix->js_order, o.tiles_per_launch, ids, sc, cnt, slots, st);
     } else {

@@ -43,10 +43,13 @@ struct Postings<float> {
 };
 
 // Write the list table of n lists (thread j < n describes list j: first entry
-// `beg`, `len` entries, weight w) and return the number of 4-entry groups in
-// the lists' concatenation.  Ends with a barrier.
+// `beg`, `len` entries, weight w, and for float lists of several queries the
+// query's score row `row` in the top bits of its meta word) and return the
+// number of 4-entry groups in the lists' concatenation.  Ends with a barrier.
+constexpr int kRowShift = 28;
 template <typename S>
-__device__ __forceinline__ uint32_t stage_write(char* stage, uint32_t* tmp, int n, int64_t beg, uint32_t len, S w) {
+__device__ __forceinline__ uint32_t stage_write(char* stage, uint32_t* tmp, int n, int64_t beg, uint32_t len, S w,
+                                                uint32_t row = 0) {
   uint32_t* pre = reinterpret_cast<uint32_t*>(stage + kPreOff);
   int64_t* cbase = reinterpret_cast<int64_t*>(stage + kCbOff);
   uint32_t* meta = reinterpret_cast<uint32_t*>(stage + kMetaOff);
@@ -59,7 +62,7 @@ __device__ __forceinline__ uint32_t stage_write(char* stage, uint32_t* tmp, int 
   if (j < n) {
     pre[j] = ex;
     cbase[j] = (beg >> 2) - int64_t(ex);
-    meta[j] = (len << 2) | off;
+    meta[j] = (row << kRowShift) | (len << 2) | off;
     w_of[j] = w;
   }
   if (j == 0) pre[n] = total;
@@ -95,13 +98,16 @@ __device__ __forceinline__ uint32_t stage_lists(char* stage, uint32_t* tmp, int6
 // list's range are added into acc at the slot they carry (the swizzled slot of
 // their row, stored by the index build) with local-memory atomics.
 // A lane only steps over the lists inside its team's range.
-// kMulti (uint8 only): the lists belong to several queries; a list's weight
-// word is (base << 8) | w and its scores go to acc + base (the query's score row).
+// kMulti: the lists belong to several queries.  uint8: a list's weight word is
+// (base << 8) | w and its scores go to acc + base (the query's score row);
+// float: the query's row index sits in the meta word's top bits and its scores
+// go to acc + row * stride.
 constexpr int kTeam = 8;
 // A: type of the score map (the staged weights are S; float lists accumulate
 // into fp64).
 template <typename V, typename S, bool kMulti = false, typename A = S>
-__device__ __forceinline__ void walk_lists(A* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P) {
+__device__ __forceinline__ void walk_lists(A* acc, const char* stage, int n_lists, uint32_t total, Postings<V> P,
+                                           int stride = 0) {
   constexpr int U = 4;
   const uint32_t* pre = reinterpret_cast<const uint32_t*>(stage + kPreOff);
   const int64_t* cbase = reinterpret_cast<const int64_t*>(stage + kCbOff);
@@ -132,6 +138,7 @@ __device__ __forceinline__ void walk_lists(A* acc, const char* stage, int n_list
     float4 ew[U];
     uint32_t rel[U], len[U];
     S ww[U];
+    [[maybe_unused]] uint32_t rw[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t g = g0 + u * kTeam;
@@ -154,7 +161,12 @@ __device__ __forceinline__ void walk_lists(A* acc, const char* stage, int n_list
           ew[u] = P.w[cb + g];
         }
         rel[u] = 4u * (g - cur) - (mt & 3u);
-        len[u] = mt >> 2;
+        if constexpr (kMulti && sizeof(V) == 4) {
+          len[u] = (mt >> 2) & ((1u << (kRowShift - 2)) - 1u);
+          rw[u] = mt >> kRowShift;
+        } else {
+          len[u] = mt >> 2;
+        }
         ww[u] = w;
       }
     }
@@ -176,9 +188,11 @@ __device__ __forceinline__ void walk_lists(A* acc, const char* stage, int n_list
       } else {
         const uint32_t sx[4] = {es[u].x & 0xffffu, es[u].x >> 16, es[u].y & 0xffffu, es[u].y >> 16};
         const float wx[4] = {ew[u].x, ew[u].y, ew[u].z, ew[u].w};
+        A* a = acc;
+        if constexpr (kMulti) a = acc + size_t(rw[u]) * stride;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&acc[sx[i]], A(ww[u]) * A(wx[i]));
+          if (rel[u] + uint32_t(i) < len[u]) atomicAdd(&a[sx[i]], A(ww[u]) * A(wx[i]));
       }
     }
   }

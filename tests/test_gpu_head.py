@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import assert_exact
+from helpers import assert_exact, assert_f32_close
 
 pytestmark = pytest.mark.gpu
 
@@ -102,10 +102,56 @@ def test_head_with_blocked_queries(zipf):
     assert_exact(got, want, "zipf head B=37")
 
 
+@pytest.fixture(scope="module")
+def zipf_f32():
+    # the float32 workload's distribution (Zipf 1.05, L2-normalised lognormal
+    # values) at a size the oracle scores in seconds; ragged last tiles
+    S = synth.draw(521, 9000, 4000, (30, 300), features="zipf", zipf_s=1.05, values="f32")
+    R = synth.draw(522, 48, 4000, (30, 300), features="zipf", zipf_s=1.05, values="f32")
+    return S, R
+
+
+@pytest.mark.parametrize("tile,head,k", [(1024, 64, 50), (2048, 128, 50), (512, 256, 5), (4096, 192, 1),
+                                         (256, 64, 100)])
+def test_f32_head_within_tolerance(zipf_f32, tile, head, k):
+    """float32 head blocks scored with fp64 products: every score within the
+    1e-5 rule of the fp64 oracle, the same walk counter as the u8 head."""
+    S, R = zipf_f32
+    print("f32 head T", tile, "H", head, "k", k, flush=True)
+    ix = kj.build_index(_dev(S), tile_width=tile, dense_head=head)
+    assert ix.dense_head == head
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    got = kj.knn_join(ix, _dev(R), k, stats=stats)
+    torch.cuda.synchronize()
+    assert_f32_close(got, R, S, range(R.n_rows), what="f32 head T=%d H=%d k=%d" % (tile, head, k))
+    assert 0 <= int(stats[kj.STAT_POSTINGS]) < oracle.postings_walked(R, S)
+    plain = kj.knn_join(ix, _dev(R), k, dense_head=False)
+    torch.cuda.synchronize()
+    assert torch.equal(got[2], plain[2])
+    torch.testing.assert_close(got[1], plain[1], rtol=1e-6, atol=0)
+
+
+def test_f32_head_edge_cases():
+    """Rows and queries with only head dimensions, only tail dimensions, none;
+    fewer than k positive scores; equal vectors (ties within rounding); a
+    partly empty workgroup of four queries."""
+    rows_s = ([[(1, 0.5), (5, 0.25)]] * 700 + [[]] + [[(9, 1.0)]] + [[(1, 0.125)]] * 300 + [[(11, 2.0)]] * 3
+              + [[(d, 0.1 * (1 + d)) for d in range(12)]])
+    S = _csr(rows_s, 12, np.float32)
+    queries = [[(1, 0.75)], [], [(5, 1.5), (9, 0.5)], [(7, 3.0)], [(1, 1.0), (5, 1.0), (9, 1.0)],
+               [(11, 0.5), (0, 4.0)], [(d, 1.0) for d in range(12)]]
+    for n_q in (len(queries), 1, 5):
+        R = _csr(queries[:n_q], 12, np.float32)
+        for k in (1, 5, 1024):
+            for tile, head in ((256, 64), (512, 128)):
+                ix = kj.build_index(_dev(S), tile_width=tile, dense_head=head)
+                got = kj.knn_join(ix, _dev(R), k)
+                torch.cuda.synchronize()
+                assert_f32_close(got, R, S, range(R.n_rows), what="f32 edge n_q=%d k=%d T=%d H=%d" % (n_q, k, tile,
+                                                                                                       head))
+
+
 def test_head_rejections():
-    f = synth.draw(11, 500, 300, (5, 20), features="uniform", values="f32")
-    with pytest.raises(kj.KnnjError):
-        kj.build_index(_dev(f), dense_head=64)
     u = synth.draw(12, 500, 300, (5, 20), features="uniform")
     for bad in (8, 16, 96, 320, -64):
         with pytest.raises(kj.KnnjError):
