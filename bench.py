@@ -409,7 +409,9 @@ def main():
     }
     print(json.dumps(res))
     bad = not ok or (iiib is not None and not all(iiib[v]["identical_to_iib"] for v in ("plain", "refined", "learned")))
-    bad = bad or (walk is not None and not walk["identical_to_dense_head"])
+    if walk is not None:
+        bad = bad or not walk.get("identical_to_dense_head", True) or not walk.get("counts_equal", True) or \
+            walk.get("max_rel_score_diff", 0.0) > 1e-5
     if bad:
         sys.exit(1)
 
