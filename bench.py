@@ -57,7 +57,7 @@ def _args():
     ap.add_argument("--no-iiib", action="store_true", help="skip the IIIB / learned-seed legs")
     ap.add_argument("--persistent", action="store_true", help="IIB: persistent per-tile launches with a work queue")
     ap.add_argument("--dense-head", type=int, default=-1,
-                    help="dimensions kept as dense per-tile blocks (-1 = 128 for u8, none for f32; 0 = plain walk)")
+                    help="dimensions kept as dense per-tile blocks (-1 = 128 for u8, 64 for f32; 0 = plain walk)")
     ap.add_argument("--tiles-per-launch", type=int, default=4, help="dense-head join: S tiles per launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -226,12 +226,15 @@ def main():
     torch.cuda.set_device(dev)
     dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
     torch.cuda.synchronize()
-    head = a.dense_head if a.dense_head >= 0 else (128 if S.values.dtype == np.uint8 else 0)
+    # dense head: 128 dimensions at T = 2048 for uint8 data, 64 at T = 1024 for float32
+    # (their fastest settings on the medium and fp32 workloads)
+    u8 = S.values.dtype == np.uint8
+    head = a.dense_head if a.dense_head >= 0 else (128 if u8 else 64)
     if a.persistent:
         head = 0
     _log("building the index")
     tb = time.time()
-    ix = kj.build_index(dS, tile_width=a.tile or (2048 if head else 0), dense_head=head)
+    ix = kj.build_index(dS, tile_width=a.tile or ((2048 if u8 else 1024) if head else 0), dense_head=head)
     torch.cuda.synchronize()
     t_build = time.time() - tb
     _log("index built in %.3fs (T=%d, %d tiles, dense head %d)" % (t_build, ix.tile_width, ix.n_tiles, head))

@@ -93,11 +93,12 @@ typedef struct {
    * workgroup's local memory (the block B_s of Algorithm 1).  0 selects the
    * default; otherwise a power of two in [256, 65536]. */
   int32_t tile_width;
-  /* uint8 data only: also keep the dense_head dimensions with the longest lists
-   * as a dense block per tile; the IIB join then computes their part of every
-   * score with byte dot products and walks only the other lists (same exact
-   * result; pays off when a few dimensions hold most postings).  0 = off;
-   * otherwise 64, 128, 192 or 256. */
+  /* Also keep the dense_head dimensions with the longest lists as a dense
+   * block per tile; the IIB join then computes their part of every score with
+   * dot products (uint8: byte dot products, the same exact sums; float32: fp64
+   * products of the float weights, each exact, summed in fp64 like the walk)
+   * and walks only the other lists.  Pays off when a few dimensions hold most
+   * postings.  0 = off; otherwise 64, 128, 192 or 256. */
   int32_t dense_head;
   int32_t reserved[6];
 } knnj_index_opts;
