@@ -244,7 +244,8 @@ typedef struct {
  * stream before it returns; block_stats (nullable, host) receives the phase
  * times.
  * Errors: as knnj_build_index and knnj_join; EINVAL for block_rows < 1 or a
- * seed.
+ * seed.  A failure after the first block leaves the outputs holding a partial
+ * result.
  */
 knnj_status knnj_join_blocked(const knnj_csr* S_host, int64_t block_rows, const knnj_index_opts* index_opts,
                               const knnj_csr* R, int32_t k, const knnj_join_opts* join_opts, int32_t* out_ids,
