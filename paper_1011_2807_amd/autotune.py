@@ -4,9 +4,9 @@ Times candidate settings on the device (HIP events around real joins of a
 query sample) and keeps the fastest:
 
 * tile width T (rows of S per tile: the LDS score array and the list split),
-* for IIB on uint8 data, the dense head (0 = plain walk, or the number of
-  longest-list dimensions kept as dense per-tile blocks) and, with a head, the
-  S tiles per launch,
+* for IIB, the dense head (0 = plain walk, or the number of longest-list
+  dimensions kept as dense per-tile blocks) and, with a head, the S tiles per
+  launch,
 * schedule (one launch per tile, or the persistent work-queue launch),
 * for IIIB, the level drop of the refined variant.
 
@@ -26,8 +26,11 @@ import torch
 
 from . import knnj as kj
 
-DEFAULT_TILES = (2048, 4096, 8192)
-CACHE_VERSION = 3  # bumped when the candidate set changes
+# candidates by value type: float32 score rows take twice the local memory, so
+# narrower tiles and heads
+DEFAULT_TILES = {"u8": (2048, 4096, 8192), "f32": (1024, 2048, 4096)}
+DEFAULT_HEADS = {"u8": (0, 128, 192), "f32": (0, 64, 128)}
+CACHE_VERSION = 4  # bumped when the candidate set changes
 
 
 def _cache_path() -> str:
@@ -78,8 +81,8 @@ def _time(fn, reps: int = 2) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", tiles: Iterable[int] = DEFAULT_TILES,
-         drops: Iterable[int] = (0, 4, 8, 12, 16, 24), heads: Iterable[int] = (0, 128, 192),
+def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", tiles: Optional[Iterable[int]] = None,
+         drops: Iterable[int] = (0, 4, 8, 12, 16, 24), heads: Optional[Iterable[int]] = None,
          tiles_per_launch: Iterable[int] = (2, 4, 8), use_cache: bool = True, verbose: bool = False) -> Dict:
     """Fastest settings for joining queries like R_sample against S.
 
@@ -88,6 +91,9 @@ def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", til
     tile_width and dense_head.
     R_sample should hold a few thousand queries drawn like the real ones.
     """
+    vt = "u8" if S.dtype == kj.KNNJ_U8 else "f32"
+    tiles = DEFAULT_TILES[vt] if tiles is None else tuple(tiles)
+    heads = DEFAULT_HEADS[vt] if heads is None else tuple(heads)
     key = signature(S, R_sample, k, algo)
     tab = _load_cache() if use_cache else {}
     if key in tab:
@@ -98,7 +104,7 @@ def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", til
            torch.empty((R_sample.n_rows, k), dtype=torch.int32 if S.dtype == kj.KNNJ_U8 else torch.float32,
                        device="cuda"),
            torch.empty(R_sample.n_rows, dtype=torch.int32, device="cuda"))
-    hs = tuple(heads) if (algo == "iib" and S.dtype == kj.KNNJ_U8) else (0,)
+    hs = heads if algo == "iib" else (0,)
     for t in tiles:
         for h in hs:
             try:

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import assert_exact
+from helpers import assert_exact, assert_f32_close
 
 pytestmark = pytest.mark.gpu
 
@@ -42,3 +42,18 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch):
     got = kj.knn_join(ix2, dR, 10, algo="iiib", bound_filter=r2["bound_filter"], level_drop=r2["level_drop"])
     torch.cuda.synchronize()
     assert_exact(got, oracle.bf_topk(R, S, 10), "tuned IIIB")
+
+
+def test_autotune_float32_heads(tmp_path, monkeypatch):
+    monkeypatch.setenv("KNNJ_TUNE_CACHE", str(tmp_path / "tune.json"))
+    S = synth.draw(531, 12_000, 4000, (30, 300), features="zipf", zipf_s=1.05, values="f32")
+    R = synth.draw(532, 200, 4000, (30, 300), features="zipf", zipf_s=1.05, values="f32")
+    dS, dR = kj.DeviceCSR.from_host(S), kj.DeviceCSR.from_host(R)
+    res = autotune.tune(dS, dR, 50, algo="iib", tiles=(1024,), heads=(0, 64))
+    # plain walk: two schedules; head 64: three launch groupings
+    assert len(res["timings"]) == 2 + 3
+    assert res["dense_head"] in (0, 64)
+    ix = kj.build_index(dS, tile_width=res["tile_width"], dense_head=res["dense_head"])
+    got = kj.knn_join(ix, dR, 50, persistent=res["persistent"], tiles_per_launch=res["tiles_per_launch"])
+    torch.cuda.synchronize()
+    assert_f32_close(got, R, S, range(R.n_rows), what="tuned f32 IIB")
