@@ -110,7 +110,8 @@ def test_batched_full_S_sampled_parity():
 def test_fp32_full_S_sampled_parity():
     """The fp32 workload's full S (10,000,000 rows, 100,000 dimensions; its IIIB
     level table exceeds 2^32 words): IIB and refined IIIB on a few hundred
-    queries, sampled rows within the fp32 rule against the fp64 oracle."""
+    queries and the dense head at the settings bench.py times, sampled rows
+    within the fp32 rule against the fp64 oracle."""
     from helpers import assert_f32_close
     S = synth.make("fp32", "S")
     R = synth.make("fp32", "R", n_rows=200)
@@ -127,3 +128,12 @@ def test_fp32_full_S_sampled_parity():
     print("IIIB done", flush=True)
     assert torch.equal(got[2], ref[2])
     assert torch.allclose(got[1], ref[1], rtol=1e-5, atol=0)
+    del ix
+    # the launch configuration bench.py times for this workload: dense head 64 at T = 1024
+    ixh = kj.build_index(dS, tile_width=1024, dense_head=64)
+    head = kj.knn_join(ixh, dR, k)
+    torch.cuda.synchronize()
+    print("dense head done", flush=True)
+    assert_f32_close(head, R, S, [0, 57, 199], what="fp32 full-S IIB dense head")
+    assert torch.equal(got[2], head[2])
+    assert torch.allclose(got[1], head[1], rtol=1e-5, atol=0)
