@@ -47,13 +47,13 @@ struct Index {
   float* post_w = nullptr;
   uint32_t* list_len = nullptr;  // |I_d| over all of S
   // dense head (optional): the head_h dimensions with the longest lists, per tile
-  // as [head_h / 16][T][16] bytes
+  // as [head_h / E][T][E] weights of the index's value type, E = 16 bytes / weight size
   int32_t head_h = 0;
   int32_t* head_pos = nullptr;   // rank of d among the head dimensions, or -1
   uint8_t* head_blk = nullptr;
   // join scratch of the dense-head join (grow-only): per query, its tail
   // features moved to the front of its CSR row (d, w) and their count, and its
-  // head weights as a dense row of head_h bytes
+  // head weights as a dense row of head_h weights (uint8 or float32 buffers)
   int64_t hj_cap_q = 0, hj_cap_nnz = 0;
   uint32_t* hj_cnt = nullptr;
   int32_t* hj_d = nullptr;

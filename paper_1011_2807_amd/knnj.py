@@ -206,8 +206,8 @@ class Index:
 
 
 def build_index(S: DeviceCSR, tile_width: int = 0, dense_head: int = 0, stream=None) -> Index:
-    """dense_head: uint8 data only; keep that many (64, 128, 192 or 256)
-    longest-list dimensions as dense per-tile blocks for the IIB join (0 = off)."""
+    """dense_head: keep that many (64, 128, 192 or 256) longest-list
+    dimensions as dense per-tile blocks for the IIB join (0 = off)."""
     lib = load_library()
     h = ctypes.c_void_p()
     opts = _IndexOpts(int(tile_width), int(dense_head))
