@@ -58,3 +58,14 @@ def test_binding_rejects_bad_arrays_before_any_call():
         kj.DeviceCSR(torch.zeros(2, dtype=torch.int64), torch.zeros(1, dtype=torch.int32),
                      torch.ones(1, dtype=torch.int16), 4)._c()
     assert knnj._require(None, "x", torch.int32, 6) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; asking for more ends with a message (before any
+    device work)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
