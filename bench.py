@@ -333,6 +333,11 @@ def main():
     iiib = None
     if not a.no_iiib:
         iiib = {}
+        # IIIB keeps a level table of n_tiles * D * 64 words per index: for float32 data over
+        # 100,000 dimensions the dense head's narrow tile (T = 1024) would need 250 GB, so the
+        # IIIB legs get an index of their own at T = 4096 (62.5 GB)
+        ixi = ix if u8 else kj.build_index(dS, tile_width=4096)
+        iiib["tile_width"] = ixi.tile_width
 
         def timed_join(label, pre=None, **kw):
             o = outs()
@@ -343,7 +348,7 @@ def main():
             e0.record(stream)
             if pre is not None:
                 kw["theta_seed"] = pre()
-            kj.knn_join(ix, dR, k, algo="iiib", validate=False, out=o, stats=st, stream=stream, **kw)
+            kj.knn_join(ixi, dR, k, algo="iiib", validate=False, out=o, stats=st, stream=stream, **kw)
             e1.record(stream)
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1)
@@ -361,14 +366,14 @@ def main():
         # allocate the index-level IIIB buffers outside the timed legs
         _log("first IIIB join (IIIB buffers)")
         one = kj.DeviceCSR(dR.indptr[:2].contiguous(), dR.indices, dR.values, dR.n_dims)
-        kj.knn_join(ix, one, k, algo="iiib", validate=False)
+        kj.knn_join(ixi, one, k, algo="iiib", validate=False)
         torch.cuda.synchronize()
         _log("first IIIB join done")
         iiib["plain"] = timed_join("iiib plain")
         # level drop of the refined variants: the autotuner's choice on a 4,000-query sample
         from paper_1011_2807_amd import autotune
         sample = kj.DeviceCSR.from_host(R.take_rows(range(min(4000, n_r))))
-        drop = autotune.tune(dS, sample, k, algo="iiib", tiles=(ix.tile_width,), drops=(4, 8, 12, 16, 24),
+        drop = autotune.tune(dS, sample, k, algo="iiib", tiles=(ixi.tile_width,), drops=(4, 8, 12, 16, 24),
                              use_cache=False)["level_drop"]
         _log("iiib level drop (autotuned): %d" % drop)
         iiib["level_drop"] = drop
@@ -378,14 +383,14 @@ def main():
         dT = kj.DeviceCSR.from_host(R_train)
         _, tsc, tcnt = kj.knn_join(ix, dT, k, validate=False)
         y = torch.where(tcnt == k, tsc[:, k - 1].float(), torch.zeros_like(tcnt, dtype=torch.float32)).contiguous()
-        Xt = kj.Mlp.features(ix, dT)
+        Xt = kj.Mlp.features(ixi, dT)
         mlp = kj.Mlp(seed=1)
         losses = mlp.train(Xt, y, epochs=8, batch=512, lr=2e-3, tau=0.05, seed=2)
         t_train = time.time() - tt
         _log("trained the seed MLP on %d queries in %.1fs, loss %.4f -> %.4f" % (n_train, t_train, losses[0],
                                                                                   losses[-1]))
         res = timed_join("iiib learned", bound_filter=True, level_drop=drop,
-                         pre=lambda: mlp.predict(kj.Mlp.features(ix, dR, stream=stream), stream=stream))
+                         pre=lambda: mlp.predict(kj.Mlp.features(ixi, dR, stream=stream), stream=stream))
         res["miss_rate"] = round(res["fallbacks"] / n_r, 4)
         res["train_queries"] = n_train
         res["train_s"] = round(t_train, 2)
