@@ -336,8 +336,8 @@ def main():
         # IIIB keeps a level table of n_tiles * D * 64 words per index: for float32 data over
         # 100,000 dimensions the dense head's narrow tile (T = 1024) would need 250 GB, so the
         # IIIB legs get an index of their own at T = 4096 (62.5 GB)
-        ixi = ix if u8 else kj.build_index(dS, tile_width=4096)
-        iiib["tile_width"] = ixi.tile_width
+        iiib_tile = ix.tile_width if u8 else 4096
+        iiib["tile_width"] = iiib_tile
 
         def timed_join(label, pre=None, **kw):
             o = outs()
@@ -363,6 +363,17 @@ def main():
             _log(label, json.dumps(res))
             return res
 
+        # level drop of the refined variants: the autotuner's choice on a 4,000-query sample.
+        # It runs first: its own index and IIIB buffers are released before those of ixi
+        # are allocated, so the two never hold device memory at once
+        from paper_1011_2807_amd import autotune
+        sample = kj.DeviceCSR.from_host(R.take_rows(range(min(4000, n_r))))
+        drop = autotune.tune(dS, sample, k, algo="iiib", tiles=(iiib_tile,), drops=(4, 8, 12, 16, 24),
+                             use_cache=False)["level_drop"]
+        del sample
+        _log("iiib level drop (autotuned): %d" % drop)
+        iiib["level_drop"] = drop
+        ixi = ix if u8 else kj.build_index(dS, tile_width=iiib_tile)
         # allocate the index-level IIIB buffers outside the timed legs
         _log("first IIIB join (IIIB buffers)")
         one = kj.DeviceCSR(dR.indptr[:2].contiguous(), dR.indices, dR.values, dR.n_dims)
@@ -370,13 +381,6 @@ def main():
         torch.cuda.synchronize()
         _log("first IIIB join done")
         iiib["plain"] = timed_join("iiib plain")
-        # level drop of the refined variants: the autotuner's choice on a 4,000-query sample
-        from paper_1011_2807_amd import autotune
-        sample = kj.DeviceCSR.from_host(R.take_rows(range(min(4000, n_r))))
-        drop = autotune.tune(dS, sample, k, algo="iiib", tiles=(ixi.tile_width,), drops=(4, 8, 12, 16, 24),
-                             use_cache=False)["level_drop"]
-        _log("iiib level drop (autotuned): %d" % drop)
-        iiib["level_drop"] = drop
         iiib["refined"] = timed_join("iiib refined", bound_filter=True, level_drop=drop)
         # learned seed: labels are the exact k-th scores of the training queries
         tt = time.time()

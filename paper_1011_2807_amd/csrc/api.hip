@@ -296,9 +296,21 @@ static int32_t* scratch_count(int64_t n) {
 // Grow the persistent-schedule scratch to n queries (the only allocation of an
 // IIB join; skipped when an earlier join was at least as large).
 static knnj_status ensure_join_scratch(Index* ix, int64_t n) {
-  if (ix->js_small == nullptr && (hipMalloc(&ix->js_small, sizeof(uint32_t) * 64) != hipSuccess ||
-                                  hipMalloc(&ix->js_heads, sizeof(uint32_t) * 2 * size_t(ix->n_tiles)) != hipSuccess))
-    return fail(KNNJ_ENOMEM, "join scratch allocation failed");
+  // both small buffers or neither: a failed pair is released so a later call retries
+  if (ix->js_small == nullptr || ix->js_heads == nullptr) {
+    (void)hipFree(ix->js_small);
+    (void)hipFree(ix->js_heads);
+    ix->js_small = nullptr;
+    ix->js_heads = nullptr;
+    if (hipMalloc(&ix->js_small, sizeof(uint32_t) * 64) != hipSuccess ||
+        hipMalloc(&ix->js_heads, sizeof(uint32_t) * 2 * size_t(ix->n_tiles)) != hipSuccess) {
+      (void)hipFree(ix->js_small);
+      (void)hipFree(ix->js_heads);
+      ix->js_small = nullptr;
+      ix->js_heads = nullptr;
+      return fail(KNNJ_ENOMEM, "join scratch allocation failed");
+    }
+  }
   if (n <= ix->js_cap) return KNNJ_OK;
   (void)hipDeviceSynchronize();
   (void)hipFree(ix->js_order);

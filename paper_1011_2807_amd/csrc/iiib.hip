@@ -513,10 +513,34 @@ constexpr unsigned kSortGrid = 4096;  // workgroups striding over the queued lon
 
 // Index-level IIIB buffers (first use) and per-query ones (grow-only).  The only
 // allocations of an IIIB join; a later join with no more queries allocates nothing.
+// Frees the per-index IIIB buffers (all of them: a partial set is never kept).
+static void free_iiib_buffers(Index* ix) {
+  void** bufs[] = {(void**)&ix->iiib_fwd,    (void**)&ix->iiib_cut,    (void**)&ix->iiib_fwd_w,
+                   (void**)&ix->iiib_post,   (void**)&ix->iiib_post_s, (void**)&ix->iiib_post_w,
+                   (void**)&ix->iiib_freq,   (void**)&ix->iiib_maxw,   (void**)&ix->iiib_big,
+                   (void**)&ix->iiib_small,  (void**)&ix->iiib_out_tmp};
+  for (void** b : bufs) {
+    (void)hipFree(*b);
+    *b = nullptr;
+  }
+}
+
+// Whether every per-index IIIB buffer of this value type is allocated.
+static bool iiib_allocated(const Index* ix) {
+  const bool common = ix->iiib_fwd && ix->iiib_cut && ix->iiib_freq && ix->iiib_maxw && ix->iiib_big &&
+                      ix->iiib_small && ix->iiib_out_tmp;
+  return common && (ix->dtype == KNNJ_U8 ? ix->iiib_post != nullptr
+                                         : (ix->iiib_post_s && ix->iiib_post_w && ix->iiib_fwd_w));
+}
+
+// Allocates the per-index IIIB buffers once, all or nothing: after a failed
+// allocation every buffer is released again, so a later call retries instead of
+// running on a partial set.
 static knnj_status ensure_iiib(Index* ix, int64_t n_r) {
   const int64_t n_keys = int64_t(ix->n_tiles) * ix->n_dims;
   const size_t nnz1 = size_t(ix->nnz > 0 ? ix->nnz : 1);
-  if (!ix->iiib_fwd) {
+  if (!iiib_allocated(ix)) {
+    free_iiib_buffers(ix);
     if (hipMalloc(&ix->iiib_fwd, sizeof(uint32_t) * nnz1) != hipSuccess ||
         hipMalloc(&ix->iiib_cut, sizeof(uint32_t) * size_t(n_keys) * kLevels) != hipSuccess ||
         (ix->dtype == KNNJ_F32 && hipMalloc(&ix->iiib_fwd_w, sizeof(float) * nnz1) != hipSuccess) ||
@@ -527,8 +551,10 @@ static knnj_status ensure_iiib(Index* ix, int64_t n_r) {
         hipMalloc(&ix->iiib_maxw, sizeof(uint32_t) * ix->n_dims) != hipSuccess ||
         hipMalloc(&ix->iiib_big, sizeof(int64_t) * (n_keys > 0 ? n_keys : 1)) != hipSuccess ||
         hipMalloc(&ix->iiib_small, sizeof(uint32_t) * 8) != hipSuccess ||
-        hipMalloc(&ix->iiib_out_tmp, sizeof(uint64_t) * nnz1) != hipSuccess)
+        hipMalloc(&ix->iiib_out_tmp, sizeof(uint64_t) * nnz1) != hipSuccess) {
+      free_iiib_buffers(ix);
       return fail(KNNJ_ENOMEM, "device allocation for the IIIB index failed");
+    }
   }
   if (n_r > ix->iiib_qcap) {
     (void)hipDeviceSynchronize();
