@@ -69,3 +69,23 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_host_csr_checks_without_a_device():
+    """HostCSR (the blocked join's S) keeps host arrays as they are and refuses
+    wrong dtypes or mismatched sizes before any library call."""
+    import numpy as np
+    import pytest
+    import synth
+    from paper_1011_2807_amd import knnj
+    m = synth.draw(3, 20, 50, (1, 10))
+    h = knnj.HostCSR(m, pin=False)
+    assert h.n_rows == 20 and h.n_dims == 50 and int(h.indices.numel()) == m.nnz
+    c = h._c()
+    assert c.n_rows == 20 and c.nnz == m.nnz and c.dtype == knnj.KNNJ_U8
+    bad = synth.CSR(m.indptr.astype(np.int32), m.indices, m.values, 50)
+    with pytest.raises(TypeError):
+        knnj.HostCSR(bad, pin=False)
+    short = synth.CSR(m.indptr, m.indices, m.values[:-1], 50)
+    with pytest.raises(ValueError):
+        knnj.HostCSR(short, pin=False)
