@@ -17,6 +17,7 @@ anything.  Cache path: $KNNJ_TUNE_CACHE or ~/.cache/knnj/tune.json.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -68,6 +69,12 @@ def signature(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str) -> str
                                                      mean_r)
 
 
+def candidates_key(tiles, heads, drops, tiles_per_launch) -> str:
+    """Short stable name of a candidate set (part of the cache key)."""
+    text = json.dumps([sorted(int(x) for x in c) for c in (tiles, heads, drops, tiles_per_launch)])
+    return "c" + hashlib.sha256(text.encode()).hexdigest()[:12]
+
+
 def _time(fn, reps: int = 2) -> float:
     fn()
     torch.cuda.synchronize()
@@ -94,7 +101,9 @@ def tune(S: kj.DeviceCSR, R_sample: kj.DeviceCSR, k: int, algo: str = "iib", til
     vt = "u8" if S.dtype == kj.KNNJ_U8 else "f32"
     tiles = DEFAULT_TILES[vt] if tiles is None else tuple(tiles)
     heads = DEFAULT_HEADS[vt] if heads is None else tuple(heads)
-    key = signature(S, R_sample, k, algo)
+    drops, tiles_per_launch = tuple(drops), tuple(tiles_per_launch)
+    # the candidate set is part of the key: a cached choice is only reused for the same candidates
+    key = signature(S, R_sample, k, algo) + "|" + candidates_key(tiles, heads, drops, tiles_per_launch)
     tab = _load_cache() if use_cache else {}
     if key in tab:
         return tab[key]

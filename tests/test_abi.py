@@ -89,3 +89,12 @@ def test_host_csr_checks_without_a_device():
     short = synth.CSR(m.indptr, m.indices, m.values[:-1], 50)
     with pytest.raises(ValueError):
         knnj.HostCSR(short, pin=False)
+
+
+def test_autotune_cache_key_names_the_candidate_set():
+    """A cached tuning result is reused only for the same candidates (any order)."""
+    from paper_1011_2807_amd import autotune
+    a = autotune.candidates_key((2048, 4096), (0, 128), (0, 4), (2, 4))
+    assert a == autotune.candidates_key((4096, 2048), (128, 0), (4, 0), (4, 2))
+    assert a != autotune.candidates_key((2048,), (0, 128), (0, 4), (2, 4))
+    assert a != autotune.candidates_key((2048, 4096), (0, 128), (0, 4, 8), (2, 4))
