@@ -22,6 +22,7 @@
 // The split rule is "index once t >= tau" with tau <= theta, so every s whose
 // score reaches theta shares an indexed feature with r (Theorem 1's argument
 // with >= in place of >): exact for running and for seeded thresholds.
+#include <mutex>
 #include <type_traits>
 
 #include "walk.hpp"
@@ -34,9 +35,14 @@ namespace knnj {
 __constant__ uint32_t c_tau_u8[kLevels];
 __constant__ float c_tau_f32[kLevels];
 
-static bool g_tau_ready = false;
+// The ladder lives in each device's constant memory: uploaded once per device.
+static std::mutex g_tau_mu;
+static bool g_tau_ready[64] = {};
 static knnj_status upload_tau() {
-  if (g_tau_ready) return KNNJ_OK;
+  int dev = -1;
+  KNNJ_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_tau_mu);
+  if (dev >= 0 && dev < 64 && g_tau_ready[dev]) return KNNJ_OK;
   uint32_t tu[kLevels];
   float tf[kLevels];
   tu[0] = 0;
@@ -47,7 +53,7 @@ static knnj_status upload_tau() {
   }
   KNNJ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tau_u8), tu, sizeof(tu)));
   KNNJ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tau_f32), tf, sizeof(tf)));
-  g_tau_ready = true;
+  if (dev >= 0 && dev < 64) g_tau_ready[dev] = true;
   return KNNJ_OK;
 }
 
