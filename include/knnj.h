@@ -112,7 +112,8 @@ typedef struct {
 /* Schedule of the IIB join.  Default: one launch per S tile with one workgroup
  * per query, queries in longest-first order (cost = the query's postings).
  * With this flag: one persistent launch per tile whose resident workgroups take
- * queries, in the same order, from a device counter.  Same results. */
+ * queries, in the same order, from a device counter.  Same results.  This
+ * schedule walks every list: an index's dense head is not used by it. */
 #define KNNJ_FLAG_PERSISTENT 4u
 /* Ignore the index's dense head: walk every list (the plain Algorithm 3 walk). */
 #define KNNJ_FLAG_NO_DENSE_HEAD 8u
